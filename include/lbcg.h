@@ -1,0 +1,156 @@
+/*
+ * lbcg.h -- C ABI of the MI355X coupled lattice Boltzmann crystal-growth solver.
+ *
+ * The solver advances three coupled lattices on one grid, as defined in Tan et al., "Mandelic
+ * acid single-crystal growth: experiments vs numerical simulations" (arXiv 2206.02145),
+ * Section 2.2:
+ *   h  phase field phi, the a_s^2-weighted stream-collide scheme Eq. (d) with the anisotropic
+ *      equilibrium Eq. (e) and source Q = phi - phi^3 + lambda U (1 - phi^2)^2;
+ *   g  supersaturation U, advection-diffusion LB with source -w dphi/dt and tau_U = D q/cs^2 + 1/2,
+ *      q = 1 - phi (Section 2.1);
+ *   f  flow, BGK with Guo forcing of the solid drag F = -h tau_f (1+phi)^2 (1-phi) u / (4 W0^2) and
+ *      the redefined velocity u* = (1-phi) u / 2 in the equilibria.
+ * Lattices: D2Q5 (phi, U) + D2Q9 (flow) in 2-D; D3Q7 + D3Q19 in 3-D. Lattice units,
+ * delta_t = delta_r = 1. Every update of one step uses time-n data only, so the three lattices
+ * are advanced by one fused kernel per step.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns lbcg_status (0 = success, < 0 = error); no C++ exception crosses the
+ *     ABI. lbcg_last_error() returns a message for the calling thread's last error.
+ *   - Device memory: the caller allocates one device workspace (lbcg_workspace_bytes) and owns
+ *     it; the library never allocates or frees device memory and keeps only a small host handle.
+ *   - Streams: all device work is enqueued on the HIP stream given at creation (a hipStream_t,
+ *     NULL for the null stream). lbcg_step only enqueues; read, write, measure and growth-rate
+ *     calls synchronise that stream before returning.
+ *   - Layout: scalar fields are [z][y][x] with x fastest; population arrays are planes
+ *     [a][z][y][x] in the lattice order
+ *       D2Q5/D3Q7 : 0, +x, -x, +y, -y, (+z, -z)
+ *       D2Q9      : 0, +x, -x, +y, -y, (1,1), (-1,-1), (1,-1), (-1,1)
+ *       D3Q19     : 0, +x, -x, +y, -y, +z, -z, (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0),
+ *                   (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1)
+ *   - Handles are not thread-safe; distinct handles may be used from distinct threads.
+ */
+#ifndef LBCG_H
+#define LBCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBCG_OK = 0,
+    LBCG_EINVAL = -1,     /* bad argument, size or field id */
+    LBCG_EUNSTABLE = -2,  /* parameters give a relaxation time <= 1/2 or a_s <= 0 */
+    LBCG_ENOMEM = -3,     /* workspace (or a destination buffer) too small */
+    LBCG_EDEVICE = -4,    /* a HIP call failed (the message names it) */
+    LBCG_ENONFINITE = -5, /* a measurement found NaN/Inf in phi, U or rho */
+    LBCG_ESTATE = -6      /* call not valid in the handle's state */
+} lbcg_status;
+
+typedef enum {
+    LBCG_FP64 = 0,         /* every population and all arithmetic in binary64 */
+    LBCG_FP32 = 1,         /* populations and arithmetic in binary32 */
+    LBCG_FP32_F16SHIFT = 2 /* as FP32, but the flow populations are stored as binary16 f_a - w_a */
+} lbcg_precision;
+
+typedef enum { LBCG_PERIODIC = 0, LBCG_INFLOW_OUTFLOW = 1 } lbcg_xbc;
+
+typedef enum {
+    LBCG_FIELD_PHI = 0,      /* phi = sum h */
+    LBCG_FIELD_U = 1,        /* U = sum g */
+    LBCG_FIELD_RHO = 2,      /* rho = sum f (1 without flow) */
+    LBCG_FIELD_UX = 3,       /* u* components: the velocity the equilibria use */
+    LBCG_FIELD_UY = 4,
+    LBCG_FIELD_UZ = 5,
+    LBCG_FIELD_PHI_PREV = 6, /* phi of the previous step (for dphi/dt) */
+    LBCG_FIELD_RAW_H = 7,    /* populations, q planes */
+    LBCG_FIELD_RAW_G = 8,
+    LBCG_FIELD_RAW_F = 9
+} lbcg_field;
+
+typedef enum { LBCG_DTYPE_F64 = 0, LBCG_DTYPE_F32 = 1 } lbcg_dtype;
+
+typedef struct {
+    int32_t dim;         /* 2 or 3 */
+    int32_t nx, ny, nz;  /* grid size; nz = 1 when dim = 2; nx >= 3 with open x faces */
+    int32_t flow;        /* 1: flow lattice on; 0: u* = 0 everywhere */
+    int32_t precision;   /* lbcg_precision */
+    int32_t xbc;         /* lbcg_xbc: periodic, or inlet at x = 0 / outlet at x = nx-1 */
+    int32_t reserved;    /* must be 0 */
+    double W0, tau0;     /* interface width and time (Eq. a); tau0 > 0, W0 > 0 */
+    double lambda;       /* coupling constant of Eq. (a) */
+    double D;            /* solute diffusivity (Eq. b); >= 0 */
+    double eps_aniso;    /* anisotropy strength, 0 <= eps < 1 */
+    double nu;           /* kinematic viscosity, > 0 with flow; tau_f = nu/cs^2 + 1/2 */
+    double h_drag;       /* drag constant h of the solid drag force (2.757 in the paper) */
+    double u_inlet;      /* inlet velocity (x) with open x faces */
+    double U0, U_inlet;  /* initial and inlet supersaturation */
+    double seed_center[3], seed_radius; /* initial seed (node coordinates; z ignored in 2-D) */
+    double grad_eps2;    /* |grad phi|^2 at or below which a_s = 1 and the anisotropy flux is 0 */
+} lbcg_params;
+
+typedef struct lbcg_handle lbcg_handle;
+typedef struct lbcg_batch lbcg_batch;
+
+/* Bytes of device workspace one solver needs (0 if the parameters are invalid). It holds two
+ * copies (ping-pong) of each population array, phi_prev, and a staging area for read-back. */
+size_t lbcg_workspace_bytes(const lbcg_params* p);
+
+/* Validate p, bind the caller's workspace (device pointer, >= lbcg_workspace_bytes bytes,
+ * 256-byte aligned) and stream, and enqueue the initial state: the seed
+ * phi0 = tanh((R - |x - c|) / (sqrt(2) W0)), h = w phi0, g = w U0,
+ * f = f_eq(rho = 1, u* = u_inlet (1 - phi0)/2 x^), phi_prev = phi0.
+ * Errors: EINVAL (sizes, enums, NULL pointers), EUNSTABLE, ENOMEM (workspace too small),
+ * EDEVICE. On error *out is NULL. */
+lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+                        lbcg_handle** out);
+
+/* Enqueue nsteps coupled time steps (Section 2.2: collide and stream h, g and f). Returns
+ * ENONFINITE without stepping if the last measurement found a non-finite value. */
+lbcg_status lbcg_step(lbcg_handle* h, int64_t nsteps);
+
+/* Number of steps taken so far. */
+int64_t lbcg_step_count(const lbcg_handle* h);
+
+/* Copy one field into dst (dst_bytes must hold it: N values, or q*N for a RAW_* field) as
+ * binary64 or binary32 values; dst is a device pointer if dst_on_device, else host memory.
+ * RAW_F of an FP16-shift solver is returned decoded (w_a + stored deviation). Synchronises. */
+lbcg_status lbcg_read_field(lbcg_handle* h, int field, void* dst, size_t dst_bytes,
+                            int dst_on_device, int dst_dtype);
+
+/* Overwrite a RAW_* population array or PHI_PREV from src (binary64 or binary32, host or
+ * device); values are rounded to the solver's storage precision. Synchronises. */
+lbcg_status lbcg_write_field(lbcg_handle* h, int field, const void* src, size_t src_bytes,
+                             int src_on_device, int src_dtype);
+
+/* Diagnostics (Section 4.1.2). mass_out[6] (may be NULL) receives, accumulated in binary64:
+ * {sum U, sum phi_prev, V_s = sum (1+phi)/2, M' = sum U + sum (1 + phi_prev), max |u*|,
+ *  number of nodes with non-finite phi, U or rho}.
+ * L_out[ndirs] (may be NULL when ndirs = 0) receives the crystal extent along each unit
+ * direction dirs[3k..3k+2] from the seed centre: the first phi = 0 crossing of a ray sampled
+ * every 1/4 cell with bi/trilinear interpolation, linearly interpolated between samples; 0 if
+ * phi <= 0 at the centre, the last in-domain distance if no crossing. Each call appends
+ * (step, L) to the handle's history for lbcg_growth_rates. Synchronises. Returns ENONFINITE
+ * (outputs filled) if a non-finite value was found. ndirs <= 256. */
+lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* L_out,
+                         double* mass_out);
+
+/* Least-squares growth rate of every direction over the recorded history (Section 4.1.2:
+ * linear fit of length against time), in cells per step: G_out[ndirs], R2_out[ndirs]
+ * (R^2 = 1 - A_res/A_tot), and *G_avg_out, the slope of the mean length. Needs >= 2 samples
+ * taken with the same ndirs (ESTATE otherwise). Any output may be NULL. */
+lbcg_status lbcg_growth_rates(lbcg_handle* h, double* G_out, double* R2_out, double* G_avg_out);
+
+/* Release the host handle (the workspace stays the caller's). NULL is accepted. */
+lbcg_status lbcg_destroy(lbcg_handle* h);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* lbcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBCG_H */

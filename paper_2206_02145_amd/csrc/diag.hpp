@@ -1,0 +1,278 @@
+// diag.hpp -- initial state, field read-back, raw population I/O and the diagnostics
+// (binary64 reductions of mass, volume and velocity; crystal-size ray-march).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+#include "step.hpp"
+
+namespace lbcg {
+
+struct SeedArgs {
+    double cx, cy, cz, R, W0, U0, u_in;
+};
+
+// Initial state: phi0 = tanh((R - |x - c|) / (sqrt(2) W0)), h = w phi0, g = w U0,
+// f = f_eq(rho = 1, u* = u_in (1 - phi0)/2 x^), phi_prev = phi0; evaluated in binary64 and
+// rounded once into the stored deviations (h + w, g - w U0, f - w, phi_prev + 1).
+template <int DIM, bool FLOW, typename real, typename fst>
+__global__ __launch_bounds__(256) void init_kernel(InstDev I, int par, SeedArgs s) {
+    using S = typename Lattices<DIM>::S;
+    using V = typename Lattices<DIM>::V;
+    const long long N = I.N;
+    real* h = static_cast<real*>(I.h[par]);
+    real* g = static_cast<real*>(I.g[par]);
+    real* pp = static_cast<real*>(I.phi_prev);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % I.nx);
+        const long long r = i / I.nx;
+        const int y = (int)(r % I.ny);
+        const int z = (int)(r / I.ny);
+        const double dx = x - s.cx, dy = y - s.cy, dz = (DIM == 3) ? z - s.cz : 0.0;
+        const double d = sqrt(dx * dx + dy * dy + dz * dz);
+        const double phi0 = tanh((s.R - d) / (sqrt(2.0) * s.W0));
+        pp[i] = (real)(phi0 + 1.0);
+#pragma unroll
+        for (int a = 0; a < S::Q; a++) {
+            h[a * N + i] = (real)(S::w(a) * (phi0 + 1.0));  // h + w
+            g[a * N + i] = (real)0;                         // g - w U0
+        }
+        if constexpr (FLOW) {
+            fst* f = static_cast<fst*>(I.f[par]);
+            const double ux = s.u_in * 0.5 * (1.0 - phi0);
+#pragma unroll
+            for (int a = 0; a < V::Q; a++) {
+                const double cu = V::c(a, 0) * ux;
+                const double dev = V::w(a) * (3.0 * cu + 4.5 * cu * cu - 1.5 * ux * ux);  // f_eq - w
+                Store<real, fst>::st_(f, a * N + i, (real)dev);
+            }
+        }
+    }
+}
+
+// Moments of one node in the compute precision: psi = phi + 1, Ut = U - U0, rho and u*.
+template <int DIM, bool FLOW, typename real, typename fst>
+__device__ inline void node_moments(const InstDev& I, int par, long long i, real& psi, real& Ut,
+                                    real& rho, real& usx, real& usy, real& usz) {
+    using S = typename Lattices<DIM>::S;
+    using V = typename Lattices<DIM>::V;
+    const long long N = I.N;
+    const real* h = static_cast<const real*>(I.h[par]);
+    const real* g = static_cast<const real*>(I.g[par]);
+    psi = 0;
+    Ut = 0;
+#pragma unroll
+    for (int a = 0; a < S::Q; a++) {
+        psi += h[a * N + i];
+        Ut += g[a * N + i];
+    }
+    rho = 1;
+    usx = usy = usz = 0;
+    if constexpr (FLOW) {
+        const fst* f = static_cast<const fst*>(I.f[par]);
+        real drho = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+        for (int a = 0; a < V::Q; a++) {
+            const real fa = Store<real, fst>::ld(f, a * N + i);
+            drho += fa;
+            if (V::c(a, 0)) mx += (real)V::c(a, 0) * fa;
+            if (V::c(a, 1)) my += (real)V::c(a, 1) * fa;
+            if (DIM == 3 && V::c(a, 2)) mz += (real)V::c(a, 2) * fa;
+        }
+        rho = (real)1 + drho;
+        const real two_m_psi = (real)2 - psi;
+        const real K = (real)I.kdrag * psi * psi * two_m_psi;
+        const real iden = (real)1 / (rho + (real)0.5 * K);
+        const real hs = (real)0.5 * two_m_psi;
+        usx = hs * mx * iden;
+        usy = hs * my * iden;
+        usz = hs * mz * iden;
+    }
+}
+
+// One macroscopic field (0 phi, 1 U, 2 rho, 3-5 u*, 6 phi_prev) into out.
+template <int DIM, bool FLOW, typename real, typename fst, typename out_t>
+__global__ __launch_bounds__(256) void field_kernel(InstDev I, int par, int field, out_t* out) {
+    const long long N = I.N;
+    const real* pp = static_cast<const real*>(I.phi_prev);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+        if (field == 6) {
+            out[i] = (out_t)((double)pp[i] - 1.0);
+            continue;
+        }
+        real psi, Ut, rho, ux, uy, uz;
+        node_moments<DIM, FLOW, real, fst>(I, par, i, psi, Ut, rho, ux, uy, uz);
+        const double v = field == 0 ? (double)psi - 1.0 : field == 1 ? (double)Ut + I.U0
+                       : field == 2 ? (double)rho : field == 3 ? (double)ux : field == 4 ? (double)uy : (double)uz;
+        out[i] = (out_t)v;
+    }
+}
+
+// One stored plane to out, decoded: value = stored deviation + shift (h: -w, g: w U0, f: w).
+template <typename real, typename st, typename out_t>
+__global__ __launch_bounds__(256) void raw_read_kernel(const st* src, long long n, double shift, out_t* out) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[i] = (out_t)((double)Store<real, st>::ld(src, i) + shift);
+}
+
+// One plane from in, encoded: stored = value - shift, rounded once to the storage type.
+template <typename real, typename st, typename in_t>
+__global__ __launch_bounds__(256) void raw_write_kernel(st* dst, long long n, double shift, const in_t* in) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        Store<real, st>::st_(dst, i, (real)((double)in[i] - shift));
+}
+
+// ---- reductions (binary64 accumulation) ----
+constexpr int RED_THREADS = 256;
+constexpr int RED_VALUES = 6;  // sumU, sumPhiPrev, Vs, M', max|u*|, nonfinite
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int DIM, bool FLOW, typename real, typename fst>
+__global__ __launch_bounds__(RED_THREADS) void reduce_kernel(InstDev I, int par, double* partials) {
+    const long long N = I.N;
+    const real* pp = static_cast<const real*>(I.phi_prev);
+    double acc[RED_VALUES] = {0, 0, 0, 0, 0, 0};
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+        real psi, Ut, rho, ux, uy, uz;
+        node_moments<DIM, FLOW, real, fst>(I, par, i, psi, Ut, rho, ux, uy, uz);
+        const double U = (double)Ut + I.U0;
+        const double psi_prev = (double)pp[i];  // phi_prev + 1
+        acc[0] += U;
+        acc[1] += psi_prev - 1.0;
+        acc[2] += 0.5 * (double)psi;      // (1 + phi) / 2
+        acc[3] += U + psi_prev;           // U + (1 + phi_prev)
+        const double um = sqrt((double)ux * ux + (double)uy * uy + (double)uz * uz);
+        acc[4] = fmax(acc[4], um);
+        if (!isfinite((double)psi) || !isfinite((double)Ut) || !isfinite((double)rho)) acc[5] += 1.0;
+    }
+    __shared__ double s[RED_THREADS / 64][RED_VALUES];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < RED_VALUES; k++) {
+        const double v = (k == 4) ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) s[wv][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < RED_VALUES) {
+        const int k = threadIdx.x;
+        double v = s[0][k];
+        for (int w = 1; w < RED_THREADS / 64; w++) v = (k == 4) ? fmax(v, s[w][k]) : v + s[w][k];
+        partials[blockIdx.x * RED_VALUES + k] = v;
+    }
+}
+
+// Fixed-order sum of the block partials (deterministic for a given launch shape).
+__global__ __launch_bounds__(64) void reduce_final(const double* partials, int nblocks, double* out) {
+    const int k = threadIdx.x;
+    if (k >= RED_VALUES) return;
+    double v = 0;
+    for (int b = 0; b < nblocks; b++) {
+        const double p = partials[b * RED_VALUES + k];
+        v = (k == 4) ? fmax(v, p) : v + p;
+    }
+    out[k] = v;
+}
+
+// ---- crystal size: ray-march along directions from the seed centre ----
+template <int DIM, typename real>
+__device__ inline double phi_node(const InstDev& I, const real* h, int x, int y, int z) {
+    using S = typename Lattices<DIM>::S;
+    const long long i = ((long long)z * I.ny + y) * I.nx + x;
+    double psi = 0;
+#pragma unroll
+    for (int a = 0; a < S::Q; a++) psi += (double)h[a * I.N + i];
+    return psi - 1.0;
+}
+
+template <int DIM, typename real>
+__device__ inline double phi_interp(const InstDev& I, const real* h, const double* pt) {
+    const int n[3] = {I.nx, I.ny, I.nz};
+    int i0[3], i1[3];
+    double t[3];
+    for (int d = 0; d < 3; d++) {
+        const double fl = floor(pt[d]);
+        i0[d] = (int)fl;
+        t[d] = pt[d] - fl;
+        if (i0[d] > n[d] - 1) i0[d] = n[d] - 1;
+        if (i0[d] < 0) i0[d] = 0;
+        i1[d] = (i0[d] + 1 < n[d]) ? i0[d] + 1 : n[d] - 1;
+    }
+    double v = 0;
+    for (int cz = 0; cz < (DIM == 3 ? 2 : 1); cz++)
+        for (int cy = 0; cy < 2; cy++)
+            for (int cx = 0; cx < 2; cx++) {
+                const double wgt = (cx ? t[0] : 1 - t[0]) * (cy ? t[1] : 1 - t[1]) *
+                                   (DIM == 3 ? (cz ? t[2] : 1 - t[2]) : 1.0);
+                if (wgt == 0.0) continue;
+                v += wgt * phi_node<DIM, real>(I, h, cx ? i1[0] : i0[0], cy ? i1[1] : i0[1],
+                                               DIM == 3 ? (cz ? i1[2] : i0[2]) : 0);
+            }
+    return v;
+}
+
+// One 64-lane workgroup per direction. Lane j of a round tests sample j+1: the first sample that
+// leaves the domain or has phi <= 0 ends the ray (all earlier samples have phi > 0).
+template <int DIM, typename real>
+__global__ __launch_bounds__(64) void raymarch_kernel(InstDev I, int par, const double* dirs,
+                                                      double cx, double cy, double cz, double* L_out) {
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
+    const real* h = static_cast<const real*>(I.h[par]);
+    const double ds = 0.25;
+    const double c[3] = {cx, cy, DIM == 3 ? cz : 0.0};
+    const double dv[3] = {dirs[3 * k], dirs[3 * k + 1], DIM == 3 ? dirs[3 * k + 2] : 0.0};
+    const double n[3] = {(double)I.nx, (double)I.ny, (double)I.nz};
+    const double phic = phi_interp<DIM, real>(I, h, c);
+    if (!(phic > 0.0)) {
+        if (lane == 0) L_out[k] = 0.0;
+        return;
+    }
+    for (long long base = 0;; base += 64) {
+        const long long j = base + lane;  // this lane tests sample j + 1 against sample j
+        const double s1 = (double)(j + 1) * ds;
+        const double pt[3] = {c[0] + s1 * dv[0], c[1] + s1 * dv[1], c[2] + s1 * dv[2]};
+        bool out = false;
+        for (int d = 0; d < (DIM == 3 ? 3 : 2); d++)
+            if (pt[d] < 0.0 || pt[d] > n[d] - 1) out = true;
+        double cur = 1.0;
+        if (!out) cur = phi_interp<DIM, real>(I, h, pt);
+        const bool ev = out || !(cur > 0.0);
+        const unsigned long long mask = __ballot(ev);
+        if (mask) {
+            const int first = __ffsll((long long)mask) - 1;
+            if (lane == first) {
+                const double sj = (double)j * ds;
+                double L;
+                if (out) {
+                    L = sj;
+                } else {
+                    const double s0 = sj;
+                    const double p0[3] = {c[0] + s0 * dv[0], c[1] + s0 * dv[1], c[2] + s0 * dv[2]};
+                    const double prev = (j == 0) ? phic : phi_interp<DIM, real>(I, h, p0);
+                    L = sj + ds * prev / (prev - cur);
+                }
+                L_out[k] = L;
+            }
+            return;
+        }
+    }
+}
+
+}  // namespace lbcg

@@ -1,0 +1,543 @@
+// lbcg_capi.hip -- host runtime and C ABI of the coupled LB crystal-growth solver (include/lbcg.h).
+//
+// The host side validates parameters, lays the caller's device workspace out into ping-pong
+// population arrays, picks the kernel instantiation for (dimension, flow, precision), enqueues
+// kernels on the caller's stream, and keeps the crystal-size history for the growth-rate fit.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/lbcg.h"
+#include "diag.hpp"
+#include "lattice.hpp"
+#include "step.hpp"
+
+using namespace lbcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error : std::runtime_error {
+    lbcg_status code;
+    Error(lbcg_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            throw Error(LBCG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+template <typename F> lbcg_status guarded(F&& fn) {
+    try {
+        fn();
+        g_err.clear();
+        return LBCG_OK;
+    } catch (const Error& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return LBCG_EDEVICE;
+    }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int qs_of(int dim) { return dim == 2 ? 5 : 7; }
+int qf_of(int dim) { return dim == 2 ? 9 : 19; }
+size_t real_size(int prec) { return prec == LBCG_FP64 ? 8 : 4; }
+size_t fstore_size(int prec) { return prec == LBCG_FP64 ? 8 : (prec == LBCG_FP32 ? 4 : 2); }
+
+constexpr int MAX_DIRS = 256;
+constexpr int RED_BLOCKS = 1024;
+
+// Validation shared by single and batched creation; throws Error.
+void validate(const lbcg_params* p) {
+    if (!p) throw Error(LBCG_EINVAL, "params is NULL");
+    if (p->dim != 2 && p->dim != 3) throw Error(LBCG_EINVAL, "dim must be 2 or 3");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) throw Error(LBCG_EINVAL, "grid sizes must be >= 1");
+    if (p->dim == 2 && p->nz != 1) throw Error(LBCG_EINVAL, "nz must be 1 when dim = 2");
+    if (p->flow != 0 && p->flow != 1) throw Error(LBCG_EINVAL, "flow must be 0 or 1");
+    if (p->precision < LBCG_FP64 || p->precision > LBCG_FP32_F16SHIFT)
+        throw Error(LBCG_EINVAL, "unknown precision");
+    if (p->precision == LBCG_FP32_F16SHIFT && !p->flow)
+        throw Error(LBCG_EINVAL, "the binary16 shifted storage applies to the flow populations (flow = 1)");
+    if (p->xbc != LBCG_PERIODIC && p->xbc != LBCG_INFLOW_OUTFLOW) throw Error(LBCG_EINVAL, "unknown xbc");
+    if (p->xbc == LBCG_INFLOW_OUTFLOW && p->nx < 3) throw Error(LBCG_EINVAL, "open x faces need nx >= 3");
+    if (p->reserved != 0) throw Error(LBCG_EINVAL, "reserved must be 0");
+    const double N = (double)p->nx * p->ny * p->nz;
+    if (N * qf_of(p->dim) > 4.0e18 / 8 || (double)p->nx * p->ny > 2.0e9)
+        throw Error(LBCG_EINVAL, "grid too large");
+    const double vals[] = {p->W0, p->tau0, p->lambda, p->D, p->eps_aniso, p->nu, p->h_drag,
+                           p->u_inlet, p->U0, p->U_inlet, p->seed_center[0], p->seed_center[1],
+                           p->seed_center[2], p->seed_radius, p->grad_eps2};
+    for (double v : vals)
+        if (!std::isfinite(v)) throw Error(LBCG_EINVAL, "non-finite parameter");
+    if (!(p->tau0 > 0) || !(p->W0 > 0))
+        throw Error(LBCG_EUNSTABLE, "tau0 and W0 must be > 0 (tau_phi = a_s^2 W0^2/(tau0 cs^2) + 1/2 > 1/2)");
+    if (!(p->eps_aniso >= 0 && p->eps_aniso < 1))
+        throw Error(LBCG_EUNSTABLE, "eps_aniso must lie in [0, 1) so that a_s > 0");
+    if (!(p->D >= 0)) throw Error(LBCG_EUNSTABLE, "D must be >= 0 (tau_U >= 1/2)");
+    if (p->flow && !(p->nu > 0)) throw Error(LBCG_EUNSTABLE, "nu must be > 0 (tau_f > 1/2)");
+    if (!(p->grad_eps2 >= 0)) throw Error(LBCG_EINVAL, "grad_eps2 must be >= 0");
+}
+
+struct Layout {
+    size_t h[2], g[2], f[2], phi_prev, staging, partials, dirs, out, total;
+};
+
+Layout layout_of(const lbcg_params* p) {
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    const size_t rs = real_size(p->precision), fs = fstore_size(p->precision);
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    for (int k = 0; k < 2; k++) L.h[k] = take(qs_of(p->dim) * N * rs);
+    for (int k = 0; k < 2; k++) L.g[k] = take(qs_of(p->dim) * N * rs);
+    for (int k = 0; k < 2; k++) L.f[k] = p->flow ? take(qf_of(p->dim) * N * fs) : 0;
+    L.phi_prev = take(N * rs);
+    L.staging = take(N * 8);
+    L.partials = take((RED_BLOCKS + 1) * RED_VALUES * 8);  // block partials, then the final values
+    L.dirs = take(MAX_DIRS * 3 * 8);
+    L.out = take((RED_VALUES + MAX_DIRS) * 8);
+    L.total = off;
+    return L;
+}
+
+InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, int TX, int TY, int TZ) {
+    InstDev I{};
+    I.nx = p->nx;
+    I.ny = p->ny;
+    I.nz = p->nz;
+    I.xopen = p->xbc == LBCG_INFLOW_OUTFLOW;
+    I.tiles_x = (p->nx + TX - 1) / TX;
+    I.tiles_y = (p->ny + TY - 1) / TY;
+    I.tiles_z = p->dim == 3 ? (p->nz + TZ - 1) / TZ : 1;
+    I.tile_begin = 0;
+    I.N = (long long)p->nx * p->ny * p->nz;
+    for (int k = 0; k < 2; k++) {
+        I.h[k] = ws + L.h[k];
+        I.g[k] = ws + L.g[k];
+        I.f[k] = p->flow ? ws + L.f[k] : nullptr;
+    }
+    I.phi_prev = ws + L.phi_prev;
+    I.k = p->W0 * p->W0 / p->tau0;
+    I.inv_tau0 = 1.0 / p->tau0;
+    I.lambda = p->lambda;
+    I.eps = p->eps_aniso;
+    I.grad_eps2 = p->grad_eps2;
+    I.D = p->D;
+    I.tau_f = p->flow ? p->nu * 3.0 + 0.5 : 1.0;
+    I.kdrag = p->h_drag * I.tau_f / (4.0 * p->W0 * p->W0);
+    I.u_in = p->u_inlet;
+    I.U_in = p->U_inlet;
+    I.U0 = p->U0;
+    return I;
+}
+
+// ---- kernel dispatch per (dim, flow, precision) ----
+struct Ops {
+    int TX, TY, TZ;
+    void (*step)(const InstDev&, int par, hipStream_t);
+    void (*init)(const InstDev&, int par, const SeedArgs&, hipStream_t);
+    void (*field)(const InstDev&, int par, int field, void* out, int dtype, hipStream_t);
+    void (*reduce)(const InstDev&, int par, double* partials, int nblocks, hipStream_t);
+    void (*ray)(const InstDev&, int par, const double* dirs, int ndirs, const double* c, double* out,
+                hipStream_t);
+};
+
+// Stored plane = value - shift: h is kept as h + w, g as g - w U0, f as f - w, phi_prev as phi_prev + 1.
+double plane_shift(const lbcg_params& p, int field, int a) {
+    const double ws = p.dim == 2 ? D2Q5::w(a) : D3Q7::w(a);
+    switch (field) {
+        case LBCG_FIELD_RAW_H: return -ws;
+        case LBCG_FIELD_RAW_G: return ws * p.U0;
+        case LBCG_FIELD_RAW_F: return p.dim == 2 ? D2Q9::w(a) : D3Q19::w(a);
+        default: return -1.0;  // PHI_PREV
+    }
+}
+
+int grid_for(long long n, int threads, int cap) {
+    long long b = (n + threads - 1) / threads;
+    if (b > cap) b = cap;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ>
+struct OpsImpl {
+    static void step(const InstDev& I, int par, hipStream_t s) {
+        const int nblocks = I.tiles_x * I.tiles_y * I.tiles_z;
+        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ>), dim3(nblocks), dim3(TX * TY * TZ),
+                           0, s, I, par);
+    }
+    static void init(const InstDev& I, int par, const SeedArgs& a, hipStream_t s) {
+        hipLaunchKernelGGL((init_kernel<DIM, FLOW, real, fst>), dim3(grid_for(I.N, 256, 65536)), dim3(256),
+                           0, s, I, par, a);
+    }
+    static void field(const InstDev& I, int par, int field, void* out, int dtype, hipStream_t s) {
+        const int nb = grid_for(I.N, 256, 65536);
+        if (dtype == LBCG_DTYPE_F64)
+            hipLaunchKernelGGL((field_kernel<DIM, FLOW, real, fst, double>), dim3(nb), dim3(256), 0, s, I, par,
+                               field, (double*)out);
+        else
+            hipLaunchKernelGGL((field_kernel<DIM, FLOW, real, fst, float>), dim3(nb), dim3(256), 0, s, I, par,
+                               field, (float*)out);
+    }
+    static void reduce(const InstDev& I, int par, double* partials, int nblocks, hipStream_t s) {
+        hipLaunchKernelGGL((reduce_kernel<DIM, FLOW, real, fst>), dim3(nblocks), dim3(RED_THREADS), 0, s, I,
+                           par, partials);
+        hipLaunchKernelGGL(reduce_final, dim3(1), dim3(64), 0, s, partials, nblocks, partials + nblocks * RED_VALUES);
+    }
+    static void ray(const InstDev& I, int par, const double* dirs, int ndirs, const double* c, double* out,
+                    hipStream_t s) {
+        hipLaunchKernelGGL((raymarch_kernel<DIM, real>), dim3(ndirs), dim3(64), 0, s, I, par, dirs, c[0], c[1],
+                           c[2], out);
+    }
+    static Ops ops() { return Ops{TX, TY, TZ, step, init, field, reduce, ray}; }
+};
+
+const Ops& ops_for(int dim, int flow, int prec) {
+    // 2-D tiles 64 x 4; 3-D tiles 32 x 4 x 4 (binary32) and 16 x 4 x 4 (binary64, LDS size).
+    static const Ops t2_nf_64 = OpsImpl<2, false, double, double, 64, 4, 1>::ops();
+    static const Ops t2_nf_32 = OpsImpl<2, false, float, float, 64, 4, 1>::ops();
+    static const Ops t2_f_64 = OpsImpl<2, true, double, double, 64, 4, 1>::ops();
+    static const Ops t2_f_32 = OpsImpl<2, true, float, float, 64, 4, 1>::ops();
+    static const Ops t2_f_16 = OpsImpl<2, true, float, __half, 64, 4, 1>::ops();
+    static const Ops t3_nf_64 = OpsImpl<3, false, double, double, 16, 4, 4>::ops();
+    static const Ops t3_nf_32 = OpsImpl<3, false, float, float, 32, 4, 4>::ops();
+    static const Ops t3_f_64 = OpsImpl<3, true, double, double, 16, 4, 4>::ops();
+    static const Ops t3_f_32 = OpsImpl<3, true, float, float, 32, 4, 4>::ops();
+    static const Ops t3_f_16 = OpsImpl<3, true, float, __half, 32, 4, 4>::ops();
+    if (dim == 2) {
+        if (!flow) return prec == LBCG_FP64 ? t2_nf_64 : t2_nf_32;
+        return prec == LBCG_FP64 ? t2_f_64 : (prec == LBCG_FP32 ? t2_f_32 : t2_f_16);
+    }
+    if (!flow) return prec == LBCG_FP64 ? t3_nf_64 : t3_nf_32;
+    return prec == LBCG_FP64 ? t3_f_64 : (prec == LBCG_FP32 ? t3_f_32 : t3_f_16);
+}
+
+}  // namespace
+
+struct lbcg_handle {
+    lbcg_params p;
+    Layout L;
+    char* ws;
+    hipStream_t stream;
+    const Ops* ops;
+    InstDev inst;
+    int par;
+    int64_t nstep;
+    int red_blocks;
+    bool nonfinite;
+    int hist_ndirs;
+    std::vector<double> hist_t;
+    std::vector<double> hist_L;  // samples x ndirs
+};
+
+extern "C" {
+
+size_t lbcg_workspace_bytes(const lbcg_params* p) {
+    try {
+        validate(p);
+        return layout_of(p).total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+                        lbcg_handle** out) {
+    if (out) *out = nullptr;
+    lbcg_handle* hdl = nullptr;
+    lbcg_status st = guarded([&] {
+        if (!out) throw Error(LBCG_EINVAL, "out is NULL");
+        validate(p);
+        Layout L = layout_of(p);
+        if (!dev_workspace) throw Error(LBCG_EINVAL, "workspace is NULL");
+        if (((uintptr_t)dev_workspace & 255) != 0) throw Error(LBCG_EINVAL, "workspace must be 256-byte aligned");
+        if (bytes < L.total)
+            throw Error(LBCG_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+        hdl = new lbcg_handle();
+        hdl->p = *p;
+        hdl->L = L;
+        hdl->ws = (char*)dev_workspace;
+        hdl->stream = (hipStream_t)hip_stream;
+        hdl->ops = &ops_for(p->dim, p->flow, p->precision);
+        hdl->inst = make_inst(p, hdl->ws, L, hdl->ops->TX, hdl->ops->TY, hdl->ops->TZ);
+        hdl->par = 0;
+        hdl->nstep = 0;
+        hdl->red_blocks = grid_for(hdl->inst.N, RED_THREADS, RED_BLOCKS);
+        hdl->nonfinite = false;
+        hdl->hist_ndirs = -1;
+        SeedArgs a{p->seed_center[0], p->seed_center[1], p->seed_center[2], p->seed_radius, p->W0, p->U0,
+                   p->flow ? p->u_inlet : 0.0};
+        // unused halves of the ping-pong buffers start defined (zero) so raw reads are reproducible
+        HIPCHK(hipMemsetAsync(hdl->ws, 0, L.staging, hdl->stream));
+        hdl->ops->init(hdl->inst, 0, a, hdl->stream);
+        HIPCHK(hipGetLastError());
+    });
+    if (st != LBCG_OK) {
+        delete hdl;
+        return st;
+    }
+    *out = hdl;
+    return LBCG_OK;
+}
+
+lbcg_status lbcg_step(lbcg_handle* h, int64_t nsteps) {
+    return guarded([&] {
+        if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
+        if (nsteps < 0) throw Error(LBCG_EINVAL, "nsteps must be >= 0");
+        if (h->nonfinite) throw Error(LBCG_ENONFINITE, "the last measurement found a non-finite value");
+        for (int64_t n = 0; n < nsteps; n++) {
+            h->ops->step(h->inst, h->par, h->stream);
+            h->par ^= 1;
+        }
+        h->nstep += nsteps;
+        HIPCHK(hipGetLastError());
+    });
+}
+
+int64_t lbcg_step_count(const lbcg_handle* h) { return h ? h->nstep : -1; }
+
+lbcg_status lbcg_read_field(lbcg_handle* h, int field, void* dst, size_t dst_bytes, int dst_on_device,
+                            int dst_dtype) {
+    return guarded([&] {
+        if (!h || !dst) throw Error(LBCG_EINVAL, "NULL handle or destination");
+        if (dst_dtype != LBCG_DTYPE_F64 && dst_dtype != LBCG_DTYPE_F32) throw Error(LBCG_EINVAL, "bad dtype");
+        if (field < LBCG_FIELD_PHI || field > LBCG_FIELD_RAW_F) throw Error(LBCG_EINVAL, "bad field id");
+        if (field == LBCG_FIELD_RAW_F && !h->p.flow) throw Error(LBCG_EINVAL, "no flow lattice");
+        const lbcg_params& p = h->p;
+        const long long N = h->inst.N;
+        const size_t es = dst_dtype == LBCG_DTYPE_F64 ? 8 : 4;
+        const int planes = field == LBCG_FIELD_RAW_H || field == LBCG_FIELD_RAW_G ? qs_of(p.dim)
+                           : field == LBCG_FIELD_RAW_F                           ? qf_of(p.dim)
+                                                                                 : 1;
+        if (dst_bytes < (size_t)planes * N * es) throw Error(LBCG_ENOMEM, "destination too small");
+        void* stage = h->ws + h->L.staging;
+        for (int a = 0; a < planes; a++) {
+            void* tgt = dst_on_device ? (char*)dst + (size_t)a * N * es : stage;
+            if (field < LBCG_FIELD_RAW_H) {
+                h->ops->field(h->inst, h->par, field, tgt, dst_dtype, h->stream);
+            } else {
+                const int nb = grid_for(N, 256, 65536);
+                const bool isF = field == LBCG_FIELD_RAW_F;
+                const double w = plane_shift(p, field, a);
+                const void* base = field == LBCG_FIELD_RAW_H ? h->inst.h[h->par]
+                                   : field == LBCG_FIELD_RAW_G ? h->inst.g[h->par]
+                                                               : h->inst.f[h->par];
+                if (p.precision == LBCG_FP64) {
+                    const double* src = (const double*)base + (size_t)a * N;
+                    if (dst_dtype == LBCG_DTYPE_F64)
+                        hipLaunchKernelGGL((raw_read_kernel<double, double, double>), dim3(nb), dim3(256), 0, h->stream,
+                                           src, N, w, (double*)tgt);
+                    else
+                        hipLaunchKernelGGL((raw_read_kernel<double, double, float>), dim3(nb), dim3(256), 0, h->stream,
+                                           src, N, w, (float*)tgt);
+                } else if (p.precision == LBCG_FP32 || !isF) {
+                    const float* src = (const float*)base + (size_t)a * N;
+                    if (dst_dtype == LBCG_DTYPE_F64)
+                        hipLaunchKernelGGL((raw_read_kernel<float, float, double>), dim3(nb), dim3(256), 0, h->stream,
+                                           src, N, w, (double*)tgt);
+                    else
+                        hipLaunchKernelGGL((raw_read_kernel<float, float, float>), dim3(nb), dim3(256), 0, h->stream,
+                                           src, N, w, (float*)tgt);
+                } else {
+                    const __half* src = (const __half*)base + (size_t)a * N;
+                    if (dst_dtype == LBCG_DTYPE_F64)
+                        hipLaunchKernelGGL((raw_read_kernel<float, __half, double>), dim3(nb), dim3(256), 0, h->stream,
+                                           src, N, w, (double*)tgt);
+                    else
+                        hipLaunchKernelGGL((raw_read_kernel<float, __half, float>), dim3(nb), dim3(256), 0, h->stream,
+                                           src, N, w, (float*)tgt);
+                }
+            }
+            HIPCHK(hipGetLastError());
+            if (!dst_on_device)
+                HIPCHK(hipMemcpyAsync((char*)dst + (size_t)a * N * es, stage, N * es, hipMemcpyDeviceToHost,
+                                      h->stream));
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+lbcg_status lbcg_write_field(lbcg_handle* h, int field, const void* src, size_t src_bytes, int src_on_device,
+                             int src_dtype) {
+    return guarded([&] {
+        if (!h || !src) throw Error(LBCG_EINVAL, "NULL handle or source");
+        if (src_dtype != LBCG_DTYPE_F64 && src_dtype != LBCG_DTYPE_F32) throw Error(LBCG_EINVAL, "bad dtype");
+        if (field != LBCG_FIELD_PHI_PREV && field != LBCG_FIELD_RAW_H && field != LBCG_FIELD_RAW_G &&
+            field != LBCG_FIELD_RAW_F)
+            throw Error(LBCG_EINVAL, "only RAW_* and PHI_PREV can be written");
+        if (field == LBCG_FIELD_RAW_F && !h->p.flow) throw Error(LBCG_EINVAL, "no flow lattice");
+        const lbcg_params& p = h->p;
+        const long long N = h->inst.N;
+        const size_t es = src_dtype == LBCG_DTYPE_F64 ? 8 : 4;
+        const int planes = field == LBCG_FIELD_RAW_H || field == LBCG_FIELD_RAW_G ? qs_of(p.dim)
+                           : field == LBCG_FIELD_RAW_F                           ? qf_of(p.dim)
+                                                                                 : 1;
+        if (src_bytes < (size_t)planes * N * es) throw Error(LBCG_ENOMEM, "source too small");
+        void* stage = h->ws + h->L.staging;
+        const int nb = grid_for(N, 256, 65536);
+        for (int a = 0; a < planes; a++) {
+            const void* in = (const char*)src + (size_t)a * N * es;
+            if (!src_on_device) {
+                HIPCHK(hipMemcpyAsync(stage, in, N * es, hipMemcpyHostToDevice, h->stream));
+                in = stage;
+            }
+            const bool isF = field == LBCG_FIELD_RAW_F;
+            const double w = plane_shift(p, field, a);
+            void* base = field == LBCG_FIELD_RAW_H   ? h->inst.h[h->par]
+                         : field == LBCG_FIELD_RAW_G ? h->inst.g[h->par]
+                         : field == LBCG_FIELD_RAW_F ? h->inst.f[h->par]
+                                                     : h->inst.phi_prev;
+            if (p.precision == LBCG_FP64) {
+                double* d = (double*)base + (size_t)a * N;
+                if (src_dtype == LBCG_DTYPE_F64)
+                    hipLaunchKernelGGL((raw_write_kernel<double, double, double>), dim3(nb), dim3(256), 0, h->stream, d,
+                                       N, w, (const double*)in);
+                else
+                    hipLaunchKernelGGL((raw_write_kernel<double, double, float>), dim3(nb), dim3(256), 0, h->stream, d,
+                                       N, w, (const float*)in);
+            } else if (p.precision == LBCG_FP32 || !isF) {
+                float* d = (float*)base + (size_t)a * N;
+                if (src_dtype == LBCG_DTYPE_F64)
+                    hipLaunchKernelGGL((raw_write_kernel<float, float, double>), dim3(nb), dim3(256), 0, h->stream, d, N,
+                                       w, (const double*)in);
+                else
+                    hipLaunchKernelGGL((raw_write_kernel<float, float, float>), dim3(nb), dim3(256), 0, h->stream, d, N,
+                                       w, (const float*)in);
+            } else {
+                __half* d = (__half*)base + (size_t)a * N;
+                if (src_dtype == LBCG_DTYPE_F64)
+                    hipLaunchKernelGGL((raw_write_kernel<float, __half, double>), dim3(nb), dim3(256), 0, h->stream, d,
+                                       N, w, (const double*)in);
+                else
+                    hipLaunchKernelGGL((raw_write_kernel<float, __half, float>), dim3(nb), dim3(256), 0, h->stream, d,
+                                       N, w, (const float*)in);
+            }
+            HIPCHK(hipGetLastError());
+            if (!src_on_device) HIPCHK(hipStreamSynchronize(h->stream));  // staging is reused per plane
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* L_out, double* mass_out) {
+    bool nonfinite = false;
+    lbcg_status st = guarded([&] {
+        if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
+        if (ndirs < 0 || ndirs > MAX_DIRS) throw Error(LBCG_EINVAL, "ndirs must be in [0, 256]");
+        if (ndirs > 0 && (!dirs || !L_out)) throw Error(LBCG_EINVAL, "dirs and L_out are required");
+        for (int k = 0; k < ndirs; k++) {
+            const double* d = dirs + 3 * k;
+            const double n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!(std::fabs(n2 - 1.0) < 1e-6)) throw Error(LBCG_EINVAL, "directions must be unit vectors");
+            if (h->p.dim == 2 && d[2] != 0.0) throw Error(LBCG_EINVAL, "2-D directions need z = 0");
+        }
+        double* part = (double*)(h->ws + h->L.partials);
+        double* ddirs = (double*)(h->ws + h->L.dirs);
+        double* dout = (double*)(h->ws + h->L.out);
+        h->ops->reduce(h->inst, h->par, part, h->red_blocks, h->stream);
+        HIPCHK(hipGetLastError());
+        if (ndirs > 0) {
+            HIPCHK(hipMemcpyAsync(ddirs, dirs, sizeof(double) * 3 * ndirs, hipMemcpyHostToDevice, h->stream));
+            h->ops->ray(h->inst, h->par, ddirs, ndirs, h->p.seed_center, dout + RED_VALUES, h->stream);
+            HIPCHK(hipGetLastError());
+        }
+        double host[RED_VALUES + MAX_DIRS];
+        HIPCHK(hipMemcpyAsync(host, part + h->red_blocks * RED_VALUES, sizeof(double) * RED_VALUES,
+                              hipMemcpyDeviceToHost, h->stream));
+        if (ndirs > 0)
+            HIPCHK(hipMemcpyAsync(host + RED_VALUES, dout + RED_VALUES, sizeof(double) * ndirs, hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        if (mass_out) std::memcpy(mass_out, host, sizeof(double) * RED_VALUES);
+        if (ndirs > 0) std::memcpy(L_out, host + RED_VALUES, sizeof(double) * ndirs);
+        if (ndirs > 0) {
+            if (h->hist_ndirs != ndirs) {
+                h->hist_ndirs = ndirs;
+                h->hist_t.clear();
+                h->hist_L.clear();
+            }
+            h->hist_t.push_back((double)h->nstep);
+            h->hist_L.insert(h->hist_L.end(), host + RED_VALUES, host + RED_VALUES + ndirs);
+        }
+        if (host[5] > 0) {
+            h->nonfinite = true;
+            nonfinite = true;
+        }
+    });
+    if (st == LBCG_OK && nonfinite) {
+        g_err = "non-finite phi, U or rho found";
+        return LBCG_ENONFINITE;
+    }
+    return st;
+}
+
+lbcg_status lbcg_growth_rates(lbcg_handle* h, double* G_out, double* R2_out, double* G_avg_out) {
+    return guarded([&] {
+        if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
+        const int K = h->hist_ndirs;
+        const size_t S = h->hist_t.size();
+        if (K <= 0 || S < 2) throw Error(LBCG_ESTATE, "need at least two measurements with directions");
+        // least squares L = b + G t per direction (Section 4.1.2), centred sums
+        double tm = 0;
+        for (double t : h->hist_t) tm += t;
+        tm /= (double)S;
+        double stt = 0;
+        for (double t : h->hist_t) stt += (t - tm) * (t - tm);
+        if (!(stt > 0)) throw Error(LBCG_ESTATE, "measurements at a single time");
+        std::vector<double> avg(S, 0.0);
+        for (size_t j = 0; j < S; j++)
+            for (int k = 0; k < K; k++) avg[j] += h->hist_L[j * K + k] / K;
+        auto fit = [&](auto getL, double& G, double& R2) {
+            double Lm = 0;
+            for (size_t j = 0; j < S; j++) Lm += getL(j);
+            Lm /= (double)S;
+            double stl = 0;
+            for (size_t j = 0; j < S; j++) stl += (h->hist_t[j] - tm) * (getL(j) - Lm);
+            G = stl / stt;
+            const double b = Lm - G * tm;
+            double ares = 0, atot = 0;
+            for (size_t j = 0; j < S; j++) {
+                const double r = getL(j) - (b + G * h->hist_t[j]);
+                ares += r * r;
+                atot += (getL(j) - Lm) * (getL(j) - Lm);
+            }
+            R2 = atot > 0 ? 1.0 - ares / atot : (ares == 0 ? 1.0 : 0.0);
+        };
+        for (int k = 0; k < K; k++) {
+            double G, R2;
+            fit([&](size_t j) { return h->hist_L[j * K + k]; }, G, R2);
+            if (G_out) G_out[k] = G;
+            if (R2_out) R2_out[k] = R2;
+        }
+        double Ga, R2a;
+        fit([&](size_t j) { return avg[j]; }, Ga, R2a);
+        if (G_avg_out) *G_avg_out = Ga;
+    });
+}
+
+lbcg_status lbcg_destroy(lbcg_handle* h) {
+    delete h;
+    return LBCG_OK;
+}
+
+const char* lbcg_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,328 @@
+// step.hpp -- the fused coupled time step (phase field h, solute g, flow f) for gfx950.
+//
+// One workgroup updates one tile of TX x TY (x TZ) nodes. Every collision of a step uses time-n
+// data only (Section 2.2 couples the lattices through phi, U and u* of the same step), so the three
+// lattices are collided and streamed in one pass:
+//
+//   phase 1: the workgroup loads h^n on the tile plus a one-node halo into LDS and forms
+//            phi = sum h there (the halo serves the isotropic gradient and the old-value term of
+//            the a_s^2-weighted stream, Eq. (d));
+//   phase 2: each thread owns one node: grad phi from LDS, the anisotropy a_s and its flux N
+//            (Eq. e), the three collisions, and a push stream of h, g and f into the other
+//            ping-pong buffer; phi_prev <- phi in place.
+//
+// Stream (push) with the a_s^2 weighting of Eq. (d), both a_s^2 taken at the collision node:
+//   h^{n+1}_a(x + c_a) = (h*_a(x) - (1 - a_s^2(x)) h^n_a(x + c_a)) / a_s^2(x).
+// Open x faces: the inlet (x = 0) bounces back the populations leaving through it (velocity
+// bounce-back for f, anti-bounce-back with U = U_in for g, plain bounce-back of Eq. (d) for h);
+// at the outlet (x = nx-1) the unknown incoming populations take the value streamed into
+// x = nx-2, which the push writes twice.
+//
+// Storage: every population array holds its deviation from a fixed reference, which keeps the
+// low-order bits where the dynamics happens and is what the binary16 mode stores:
+//   h~ = h + w   (so sum h~ = psi = phi + 1, ~0 in the liquid),
+//   g~ = g - w U0 (sum g~ = U - U0, 0 at the start),
+//   f~ = f - w   (sum f~ = rho - 1),
+// and phi_prev is kept as psi_prev = phi_prev + 1. The collisions are written in these variables;
+// the a_s^2-weighted stream is unchanged by the shift because w_a = w_{opposite(a)}.
+//
+// HBM traffic per node: every population read once and written once, plus phi_prev read and
+// written; halo re-reads of h are served by LDS and L2.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lattice.hpp"
+
+namespace lbcg {
+
+// Per-instance descriptor, shared by the single-grid and the batched launches.
+struct InstDev {
+    int nx, ny, nz, xopen;
+    int tiles_x, tiles_y, tiles_z, tile_begin;
+    long long N;                  // nodes
+    void* h[2];                   // ping-pong population arrays, planes [a][z][y][x]
+    void* g[2];
+    void* f[2];
+    void* phi_prev;
+    double k;                     // W0^2 / tau0
+    double inv_tau0, lambda, eps, grad_eps2, D;
+    double tau_f, kdrag;          // kdrag = h_drag tau_f / (4 W0^2)
+    double u_in, U_in, U0;
+};
+
+// Population storage type: the compute type, or binary16 (deviation stored round-to-nearest-even).
+template <typename real, typename st> struct Store {
+    __device__ static inline real ld(const st* p, long long i) { return p[i]; }
+    __device__ static inline void st_(st* p, long long i, real v) { p[i] = v; }
+};
+template <> struct Store<float, __half> {
+    __device__ static inline float ld(const __half* p, long long i) { return __half2float(p[i]); }
+    __device__ static inline void st_(__half* p, long long i, float v) { p[i] = __float2half_rn(v); }
+};
+
+__device__ __forceinline__ int wrap_coord(int v, int n) {
+    if (v < 0) v += n;
+    if (v >= n) v -= n;
+    if (v < 0 || v >= n) {
+        v %= n;
+        if (v < 0) v += n;
+    }
+    return v;
+}
+
+// Workgroup -> tile map that gives each of the 8 XCDs (workgroups are dealt round-robin to
+// them) one contiguous range of tiles, so halo re-reads stay in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+    const int xcd = b & 7, idx = b >> 3;
+    const int per = nblocks >> 3, rem = nblocks & 7;
+    return xcd * per + (xcd < rem ? xcd : rem) + idx;
+}
+
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ>
+__device__ __forceinline__ void step_tile(const InstDev& I, const int tile, const int par) {
+    using S = typename Lattices<DIM>::S;
+    using V = typename Lattices<DIM>::V;
+    constexpr int NT = TX * TY * TZ;
+    constexpr int BX = TX + 2, BY = TY + 2, BZ = (DIM == 3) ? TZ + 2 : 1;
+    constexpr int NB = BX * BY * BZ;
+    constexpr int SY = BX, SZ = BX * BY;  // LDS strides
+    __shared__ real s_phi[NB];
+    __shared__ real s_h[S::Q][NB];
+
+    const int tid = threadIdx.x;
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const long long N = I.N;
+    const int tix = tile % I.tiles_x;
+    const int trest = tile / I.tiles_x;
+    const int tiy = trest % I.tiles_y;
+    const int tiz = trest / I.tiles_y;
+    const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
+
+    const real* __restrict__ hin = static_cast<const real*>(I.h[par]);
+    real* __restrict__ hout = static_cast<real*>(I.h[par ^ 1]);
+    const real* __restrict__ gin = static_cast<const real*>(I.g[par]);
+    real* __restrict__ gout = static_cast<real*>(I.g[par ^ 1]);
+    real* __restrict__ pprev = static_cast<real*>(I.phi_prev);
+
+    // ---- phase 1: h and phi on the tile + halo ----
+    for (int b = tid; b < NB; b += NT) {
+        const int bx = b % BX;
+        const int br = b / BX;
+        const int by = br % BY;
+        const int bz = br / BY;
+        int gx = x0 + bx - 1;
+        if (I.xopen) gx = gx < 0 ? 0 : (gx > nx - 1 ? nx - 1 : gx);  // ghost = face node
+        else gx = wrap_coord(gx, nx);
+        const int gy = wrap_coord(y0 + by - 1, ny);
+        const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
+        const long long gi = ((long long)gz * ny + gy) * nx + gx;
+        real phi = 0;
+#pragma unroll
+        for (int a = 0; a < S::Q; a++) {
+            const real v = hin[a * N + gi];
+            s_h[a][b] = v;
+            phi += v;
+        }
+        s_phi[b] = phi;
+    }
+    __syncthreads();
+
+    // ---- phase 2: one node per thread ----
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    if (x >= nx || y >= ny || z >= nz) return;
+    const int bo = (DIM == 3 ? (lz + 1) * SZ : 0) + (ly + 1) * SY + (lx + 1);
+    const long long gi = ((long long)z * ny + y) * nx + x;
+
+    // neighbour coordinates; -1 marks "through the inlet", nx marks "through the outlet"
+    const bool xopen = I.xopen != 0;
+    const int xp = (x + 1 < nx) ? x + 1 : (xopen ? nx : 0);
+    const int xm = (x > 0) ? x - 1 : (xopen ? -1 : nx - 1);
+    const int yp = (y + 1 < ny) ? y + 1 : 0;
+    const int ym = (y > 0) ? y - 1 : ny - 1;
+    const int zp = (DIM == 3) ? ((z + 1 < nz) ? z + 1 : 0) : 0;
+    const int zm = (DIM == 3) ? ((z > 0) ? z - 1 : nz - 1) : 0;
+    auto dst_x = [&](int cx) { return cx > 0 ? xp : (cx < 0 ? xm : x); };
+    auto row = [&](int cy, int cz) -> long long {
+        const int yy = cy > 0 ? yp : (cy < 0 ? ym : y);
+        const int zz = cz > 0 ? zp : (cz < 0 ? zm : z);
+        return ((long long)zz * ny + yy) * nx;
+    };
+    const bool at_outlet = xopen && (x == nx - 1);
+
+    const real psi = s_phi[bo];  // phi + 1
+    const real phi = psi - (real)1;
+    const real two_m_psi = (real)2 - psi;  // 1 - phi
+    const real p2 = psi * two_m_psi;       // 1 - phi^2
+
+    // grad phi = (1/cs^2) sum_b w_b c_b phi(x + c_b), D2Q9 / D3Q19 stencil (the shift cancels)
+    real px = 0, py = 0, pz = 0;
+#pragma unroll
+    for (int b = 1; b < V::Q; b++) {
+        const real ph = s_phi[bo + V::c(b, 0) + V::c(b, 1) * SY + (DIM == 3 ? V::c(b, 2) * SZ : 0)];
+        const real wc = (real)(V::w(b) * V::inv_cs2);
+        if (V::c(b, 0)) px += (real)V::c(b, 0) * wc * ph;
+        if (V::c(b, 1)) py += (real)V::c(b, 1) * wc * ph;
+        if (DIM == 3 && V::c(b, 2)) pz += (real)V::c(b, 2) * wc * ph;
+    }
+
+    // anisotropy a_s = 1 + eps Re((nx + i ny)^6) and its flux N = 2 eps a_s |p| (grad P - 6 P n)
+    const real eps = (real)I.eps;
+    real as = 1, Nx = 0, Ny = 0, Nz = 0;
+    const real s2 = px * px + py * py + pz * pz;
+    if (s2 > (real)I.grad_eps2) {
+        const real m = sqrt(s2);
+        const real im = (real)1 / m;
+        const real ux_ = px * im, uy_ = py * im, uz_ = pz * im;
+        const real z2r = ux_ * ux_ - uy_ * uy_, z2i = (real)2 * ux_ * uy_;
+        const real z4r = z2r * z2r - z2i * z2i, z4i = (real)2 * z2r * z2i;
+        const real z5r = z4r * ux_ - z4i * uy_, z5i = z4r * uy_ + z4i * ux_;
+        const real P6 = z5r * ux_ - z5i * uy_;
+        as = (real)1 + eps * P6;
+        const real c2 = (real)2 * eps * as * m;
+        Nx = c2 * ((real)6 * z5r - (real)6 * P6 * ux_);
+        Ny = c2 * ((real)-6 * z5i - (real)6 * P6 * uy_);
+        Nz = c2 * ((real)-6 * P6 * uz_);
+    }
+    const real a2 = as * as;
+    const real inv_a2 = (real)1 / a2;
+    const real one_m_a2 = (real)1 - a2;
+
+    // solute moment: Ut = U - U0
+    real gv[S::Q];
+    real Ut = 0;
+#pragma unroll
+    for (int a = 0; a < S::Q; a++) {
+        gv[a] = gin[a * N + gi];
+        Ut += gv[a];
+    }
+    const real U = Ut + (real)I.U0;
+
+    // ---- phase field: Eq. (d) with the equilibrium of Eq. (e) ----
+    {
+        const real kc = (real)(I.k * S::inv_cs2);  // (W0^2/tau0)/cs^2
+        const real inv_tau_phi = (real)1 / (a2 * kc + (real)0.5);
+        // Q = phi - phi^3 + lambda U (1 - phi^2)^2 = (1 - phi^2)(phi + lambda U (1 - phi^2))
+        const real Qs = p2 * (phi + (real)I.lambda * U * p2) * (real)I.inv_tau0;
+#pragma unroll
+        for (int a = 0; a < S::Q; a++) {
+            const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
+            const real wa = (real)S::w(a);
+            const real cN = (real)cx * Nx + (real)cy * Ny + (real)cz * Nz;
+            const real heq = wa * (psi - cN * kc);  // h_eq + w
+            const real ha = s_h[a][bo];
+            const real hs = ha - (ha - heq) * inv_tau_phi + wa * Qs;
+            const int xd = dst_x(cx);
+            if (xd >= 0 && xd < nx) {
+                const real hnb = s_h[a][bo + cx + cy * SY + (DIM == 3 ? cz * SZ : 0)];
+                const real v = (hs - one_m_a2 * hnb) * inv_a2;
+                hout[a * N + row(cy, cz) + xd] = v;
+                if (cx < 0 && at_outlet) hout[a * N + row(cy, cz) + x] = v;
+            } else if (xd < 0) {  // inlet: bounce back into the opposite slot of this node
+                const int b = S::opp(a);
+                const real v = (hs - one_m_a2 * s_h[b][bo]) * inv_a2;
+                hout[b * N + gi] = v;
+            }
+        }
+    }
+
+    // ---- flow: BGK + Guo forcing of the drag, u* in the equilibrium ----
+    real usx = 0, usy = 0, usz = 0;
+    if constexpr (FLOW) {
+        const fst* __restrict__ fin = static_cast<const fst*>(I.f[par]);
+        fst* __restrict__ fout = static_cast<fst*>(I.f[par ^ 1]);
+        real fv[V::Q];
+        real drho = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+        for (int a = 0; a < V::Q; a++) {
+            fv[a] = Store<real, fst>::ld(fin, a * N + gi);  // f - w
+            drho += fv[a];
+            if (V::c(a, 0)) mx += (real)V::c(a, 0) * fv[a];
+            if (V::c(a, 1)) my += (real)V::c(a, 1) * fv[a];
+            if (DIM == 3 && V::c(a, 2)) mz += (real)V::c(a, 2) * fv[a];
+        }
+        const real rho = (real)1 + drho;
+        const real K = (real)I.kdrag * psi * psi * two_m_psi;  // (1+phi)^2 (1-phi)
+        const real iden = (real)1 / (rho + (real)0.5 * K);
+        const real ux = mx * iden, uy = my * iden, uz = mz * iden;
+        const real Fx = -K * ux, Fy = -K * uy, Fz = -K * uz;
+        const real hs_ = (real)0.5 * two_m_psi;
+        usx = hs_ * ux;
+        usy = hs_ * uy;
+        usz = hs_ * uz;
+        const real uu = usx * usx + usy * usy + usz * usz;
+        const real uF = usx * Fx + usy * Fy + usz * Fz;
+        const real inv_tau_f = (real)(1.0 / I.tau_f);
+        const real guo = (real)(1.0 - 0.5 / I.tau_f);
+        const real uinx = (real)I.u_in;
+#pragma unroll
+        for (int a = 0; a < V::Q; a++) {
+            const int cx = V::c(a, 0), cy = V::c(a, 1), cz = V::c(a, 2);
+            const real wa = (real)V::w(a);
+            const real cu = (real)cx * usx + (real)cy * usy + (real)cz * usz;
+            const real cF = (real)cx * Fx + (real)cy * Fy + (real)cz * Fz;
+            // f_eq - w = w [rho - 1 + rho (cu/cs2 + cu^2/(2 cs2^2) - uu/(2 cs2))]
+            const real feq = wa * (drho + rho * ((real)3 * cu + (real)4.5 * cu * cu - (real)1.5 * uu));
+            const real Sa = wa * guo * ((real)3 * cF + (real)9 * cu * cF - (real)3 * uF);
+            const real fs = fv[a] - (fv[a] - feq) * inv_tau_f + Sa;
+            const int xd = dst_x(cx);
+            if (xd >= 0 && xd < nx) {
+                Store<real, fst>::st_(fout, a * N + row(cy, cz) + xd, fs);
+                if (cx < 0 && at_outlet) Store<real, fst>::st_(fout, a * N + row(cy, cz) + x, fs);
+            } else if (xd < 0) {  // velocity bounce-back, wall density 1
+                const int b = V::opp(a);
+                Store<real, fst>::st_(fout, b * N + gi, fs - (real)6 * wa * (real)cx * uinx);
+            }
+        }
+    }
+
+    // ---- solute: advection-diffusion LB with source -w dphi/dt ----
+    {
+        real q = two_m_psi;  // 1 - phi, clamped to [0, 2]
+        q = q < (real)0 ? (real)0 : (q > (real)2 ? (real)2 : q);
+        const real inv_tau_U = (real)1 / ((real)(I.D * S::inv_cs2) * q + (real)0.5);
+        const real dphi = psi - pprev[gi];
+        const real Uin2 = (real)2 * (real)(I.U_in - I.U0);
+#pragma unroll
+        for (int a = 0; a < S::Q; a++) {
+            const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
+            const real wa = (real)S::w(a);
+            const real cu = (real)cx * usx + (real)cy * usy + (real)cz * usz;
+            const real geq = wa * (Ut + U * cu * (real)S::inv_cs2);  // g_eq - w U0
+            const real gs = gv[a] - (gv[a] - geq) * inv_tau_U - wa * dphi;
+            const int xd = dst_x(cx);
+            if (xd >= 0 && xd < nx) {
+                gout[a * N + row(cy, cz) + xd] = gs;
+                if (cx < 0 && at_outlet) gout[a * N + row(cy, cz) + x] = gs;
+            } else if (xd < 0) {  // anti-bounce-back, U = U_in on the inlet wall
+                gout[S::opp(a) * N + gi] = -gs + wa * Uin2;
+            }
+        }
+    }
+    pprev[gi] = psi;
+}
+
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX* TY* TZ) void step_single(InstDev I, int par) {
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ>(I, xcd_tile(blockIdx.x, gridDim.x), par);
+}
+
+// Batched launch: the tiles of all instances form one list; each workgroup finds its instance
+// by binary search over the tile offsets.
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ>
+__global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restrict__ insts, int ninst,
+                                                         int par) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (insts[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const InstDev I = insts[lo];
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ>(I, t - I.tile_begin, par);
+}
+
+}  // namespace lbcg

@@ -1,0 +1,198 @@
+"""ctypes binding of liblbcg.so (include/lbcg.h): argument marshalling only.
+
+Every step of the solver runs in the HIP kernels of the library; PyTorch provides the device
+workspace and the stream. There is no CPU fallback: without the built library or a HIP device
+these functions raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbcg.so")
+
+LBCG_OK = 0
+STATUS = {0: "OK", -1: "EINVAL", -2: "EUNSTABLE", -3: "ENOMEM", -4: "EDEVICE", -5: "ENONFINITE",
+          -6: "ESTATE"}
+PRECISION = {"fp64": 0, "fp32": 1, "fp16shift": 2}
+FIELD = {"phi": 0, "U": 1, "rho": 2, "ux": 3, "uy": 4, "uz": 5, "phi_prev": 6, "raw_h": 7,
+         "raw_g": 8, "raw_f": 9}
+DTYPE = {np.float64: 0, np.float32: 1}
+
+
+class lbcg_params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32), ("flow", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("xbc", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("W0", ctypes.c_double), ("tau0", ctypes.c_double), ("lambda_", ctypes.c_double),
+        ("D", ctypes.c_double), ("eps_aniso", ctypes.c_double), ("nu", ctypes.c_double),
+        ("h_drag", ctypes.c_double), ("u_inlet", ctypes.c_double), ("U0", ctypes.c_double),
+        ("U_inlet", ctypes.c_double), ("seed_center", ctypes.c_double * 3),
+        ("seed_radius", ctypes.c_double), ("grad_eps2", ctypes.c_double),
+    ]
+
+
+class LbcgError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+        dp = ctypes.POINTER(ctypes.c_double)
+        pp = ctypes.POINTER(lbcg_params)
+        L.lbcg_workspace_bytes.argtypes = [pp]
+        L.lbcg_workspace_bytes.restype = sz
+        L.lbcg_create.argtypes = [pp, vp, sz, vp, ctypes.POINTER(vp)]
+        L.lbcg_step.argtypes = [vp, i64]
+        L.lbcg_step_count.argtypes = [vp]
+        L.lbcg_step_count.restype = i64
+        L.lbcg_read_field.argtypes = [vp, i32, vp, sz, i32, i32]
+        L.lbcg_write_field.argtypes = [vp, i32, vp, sz, i32, i32]
+        L.lbcg_measure.argtypes = [vp, i32, dp, dp, dp]
+        L.lbcg_growth_rates.argtypes = [vp, dp, dp, dp]
+        L.lbcg_destroy.argtypes = [vp]
+        L.lbcg_last_error.argtypes = []
+        L.lbcg_last_error.restype = ctypes.c_char_p
+        for name in ("lbcg_create", "lbcg_step", "lbcg_read_field", "lbcg_write_field",
+                     "lbcg_measure", "lbcg_growth_rates", "lbcg_destroy"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def check(code: int, where: str):
+    if code != LBCG_OK:
+        raise LbcgError(code, where, lib().lbcg_last_error().decode())
+
+
+def make_params(p: dict, precision: str = "fp32") -> lbcg_params:
+    """lbcg_params from a parameter dict (keys as in paper_2206_02145_amd.workloads)."""
+    s = lbcg_params()
+    s.dim, s.nx, s.ny, s.nz = int(p["dim"]), int(p["nx"]), int(p["ny"]), int(p["nz"])
+    s.flow, s.xbc, s.reserved = int(p["flow"]), int(p["xbc"]), 0
+    s.precision = PRECISION[precision]
+    s.W0, s.tau0, s.lambda_, s.D = p["W0"], p["tau0"], p["lam"], p["D"]
+    s.eps_aniso, s.nu, s.h_drag = p["eps"], p["nu"], p["h_drag"]
+    s.u_inlet, s.U0, s.U_inlet = p["u_in"], p["U0"], p["U_in"]
+    for d in range(3):
+        s.seed_center[d] = float(p["seed_c"][d])
+    s.seed_radius, s.grad_eps2 = p["seed_R"], p["grad_eps2"]
+    return s
+
+
+def lbcg_workspace_bytes(params: lbcg_params) -> int:
+    return int(lib().lbcg_workspace_bytes(ctypes.byref(params)))
+
+
+def _dptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Solver:
+    """One grid: owns a torch device workspace and a library handle."""
+
+    def __init__(self, p: dict, precision: str = "fp32", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the lbcg solver needs a HIP device")
+        self.p = dict(p)
+        self.precision = precision
+        self.params = make_params(p, precision)
+        nbytes = lbcg_workspace_bytes(self.params)
+        if nbytes == 0:
+            # reproduce the validation error message through lbcg_create
+            h = ctypes.c_void_p()
+            check(lib().lbcg_create(ctypes.byref(self.params), None, 0, None, ctypes.byref(h)), "lbcg_create")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = ctypes.c_void_p()
+        check(lib().lbcg_create(ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.handle)),
+              "lbcg_create")
+        self.shape = (int(p["nz"]), int(p["ny"]), int(p["nx"]))
+        self.qs = 5 if p["dim"] == 2 else 7
+        self.qf = 9 if p["dim"] == 2 else 19
+
+    def step(self, n: int = 1):
+        check(lib().lbcg_step(self.handle, int(n)), "lbcg_step")
+
+    @property
+    def nstep(self) -> int:
+        return int(lib().lbcg_step_count(self.handle))
+
+    def _planes(self, field: str) -> int:
+        return {"raw_h": self.qs, "raw_g": self.qs, "raw_f": self.qf}.get(field, 1)
+
+    def read(self, field: str, dtype=np.float64) -> np.ndarray:
+        """Field as a host numpy array: (nz, ny, nx), or (q, nz, ny, nx) for raw_*."""
+        k = self._planes(field)
+        shape = ((k,) if k > 1 or field.startswith("raw") else ()) + self.shape
+        out = np.empty(shape, dtype=dtype)
+        check(lib().lbcg_read_field(self.handle, FIELD[field], out.ctypes.data, out.nbytes, 0,
+                                    DTYPE[np.dtype(dtype).type]), "lbcg_read_field")
+        return out
+
+    def read_device(self, field: str, dtype=None):
+        """Field into a new torch tensor on the device."""
+        import torch
+        dtype = dtype or torch.float64
+        k = self._planes(field)
+        shape = ((k,) if field.startswith("raw") else ()) + self.shape
+        out = torch.empty(shape, dtype=dtype, device="cuda")
+        code = 0 if dtype == torch.float64 else 1
+        check(lib().lbcg_read_field(self.handle, FIELD[field], ctypes.c_void_p(out.data_ptr()),
+                                    out.numel() * out.element_size(), 1, code), "lbcg_read_field")
+        return out
+
+    def write(self, field: str, arr: np.ndarray):
+        arr = np.ascontiguousarray(arr)
+        if arr.dtype not in (np.float64, np.float32):
+            arr = arr.astype(np.float64)
+        check(lib().lbcg_write_field(self.handle, FIELD[field], arr.ctypes.data, arr.nbytes, 0,
+                                     DTYPE[arr.dtype.type]), "lbcg_write_field")
+
+    def measure(self, dirs=None, raise_nonfinite: bool = True):
+        """(L [ndirs], mass dict) -- see lbcg_measure."""
+        dirs = np.zeros((0, 3)) if dirs is None else np.ascontiguousarray(dirs, dtype=np.float64)
+        nd = dirs.shape[0]
+        L = np.zeros(max(nd, 1))
+        m = np.zeros(6)
+        code = lib().lbcg_measure(self.handle, nd, _dptr(dirs) if nd else None, _dptr(L), _dptr(m))
+        if code != -5 or raise_nonfinite:
+            check(code, "lbcg_measure")
+        mass = dict(sumU=m[0], sumPhiPrev=m[1], Vs=m[2], Mprime=m[3], umax=m[4], nonfinite=m[5])
+        return L[:nd], mass
+
+    def growth_rates(self, ndirs: int):
+        G = np.zeros(ndirs)
+        R2 = np.zeros(ndirs)
+        Ga = ctypes.c_double()
+        check(lib().lbcg_growth_rates(self.handle, _dptr(G), _dptr(R2), ctypes.byref(Ga)), "lbcg_growth_rates")
+        return G, R2, Ga.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lbcg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,87 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every entry point
+include/lbcg.h declares, sizes workspaces, and rejects bad parameters before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2206_02145_amd import lbcg
+from paper_2206_02145_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(lbcg_\w+)\s*\(", txt, flags=re.M))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbcg.lib()
+    names = declared_functions()
+    assert "lbcg_create" in names and "lbcg_step" in names and len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("cfg,prec,qs,qf,rs,fs", [
+    (W.config1(), "fp64", 5, 0, 8, 0),
+    (W.config2(), "fp32", 7, 0, 4, 0),
+    (W.config3(), "fp32", 7, 19, 4, 4),
+    (W.config3(), "fp16shift", 7, 19, 4, 2),
+])
+def test_workspace_bytes(cfg, prec, qs, qf, rs, fs):
+    n = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    b = lbcg.lbcg_workspace_bytes(lbcg.make_params(cfg, prec))
+    core = 2 * qs * n * rs * 2 + 2 * qf * n * fs + n * rs  # ping-pong h, g, f and phi_prev
+    assert core + 8 * n <= b <= core + 8 * n + 64 * 1024
+
+
+def create_status(p, prec="fp32", nbytes=None):
+    params = lbcg.make_params(p, prec)
+    h = ctypes.c_void_p()
+    n = lbcg.lbcg_workspace_bytes(params) if nbytes is None else nbytes
+    # a non-NULL, aligned fake pointer: validation fails before any device access
+    return lbcg.lib().lbcg_create(ctypes.byref(params), ctypes.c_void_p(1 << 20), n, None, ctypes.byref(h)), h
+
+
+@pytest.mark.parametrize("change,expect", [
+    (dict(dim=4), "EINVAL"),
+    (dict(nz=3), "EINVAL"),           # 2-D with nz != 1
+    (dict(nx=0), "EINVAL"),
+    (dict(xbc=1, nx=2), "EINVAL"),
+    (dict(eps=1.0), "EUNSTABLE"),
+    (dict(tau0=0.0), "EUNSTABLE"),
+    (dict(W0=-1.0), "EUNSTABLE"),
+    (dict(D=-0.1), "EUNSTABLE"),
+    (dict(flow=1, nu=0.0), "EUNSTABLE"),
+    (dict(U0=float("nan")), "EINVAL"),
+])
+def test_create_rejects_bad_parameters(change, expect):
+    p = W.params(**change)
+    assert lbcg.lbcg_workspace_bytes(lbcg.make_params(p)) == 0
+    code, h = create_status(p, nbytes=1 << 30)
+    assert lbcg.STATUS[code] == expect, lbcg.lib().lbcg_last_error()
+    assert not h.value
+    assert lbcg.lib().lbcg_last_error()
+
+
+def test_create_rejects_small_workspace_and_fp16_without_flow():
+    p = W.params()
+    n = lbcg.lbcg_workspace_bytes(lbcg.make_params(p))
+    code, _ = create_status(p, nbytes=n - 1)
+    assert lbcg.STATUS[code] == "ENOMEM"
+    code, _ = create_status(W.params(flow=0), prec="fp16shift", nbytes=1 << 30)
+    assert lbcg.STATUS[code] == "EINVAL"
+
+
+def test_null_handles_are_rejected():
+    L = lbcg.lib()
+    assert lbcg.STATUS[L.lbcg_step(None, 1)] == "EINVAL"
+    assert lbcg.STATUS[L.lbcg_measure(None, 0, None, None, None)] == "EINVAL"
+    assert L.lbcg_destroy(None) == 0

@@ -1,0 +1,236 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Error metric per field: ||x - x_ref||_inf / ||x_ref||_inf. Bars: binary64 path <= 1e-10 (the
+same algorithm, rounding differences only); binary32 path <= 1e-4; the binary16-shift storage of
+the flow populations is reported per field against a looser bar.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2206_02145_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-4, "fp16shift": 5e-3}
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2206_02145_amd import lbcg
+    lbcg.lib()
+    return lbcg
+
+
+def relerr(a, b):
+    den = np.abs(b).max()
+    return np.abs(a - b).max() / (den if den > 0 else 1.0)
+
+
+def field_errors(read, rf, fields):
+    """Per-field error; the velocity u* is compared as a vector (max component error over the
+    largest reference component), since a near-zero component has no scale of its own."""
+    errs = {}
+    for name in fields:
+        if name in ("ux", "uy", "uz"):
+            continue
+        errs[name] = relerr(read(name), rf[name])
+    comps = [c for c in ("ux", "uy", "uz") if c in fields]
+    umax = max([np.abs(rf[c]).max() for c in comps] + [0.0])
+    if comps and umax > 0:
+        errs["u"] = max(np.abs(read(c) - rf[c]).max() for c in comps) / umax
+    return errs
+
+
+def compare(lb, orc, p, prec, steps, fields=("phi", "U", "rho", "ux", "uy", "uz"), tol=None, label=""):
+    print(f"[parity] {label} {prec} grid={p['nx']}x{p['ny']}x{p['nz']} flow={p['flow']} "
+          f"xbc={p['xbc']} steps={steps}", flush=True)
+    ref = orc.Sim(p)
+    ref.step(steps)
+    rf = ref.fields()
+    s = lb.Solver(p, prec)
+    s.step(steps)
+    errs = field_errors(s.read, rf, fields)
+    errs["phi_prev"] = relerr(s.read("phi_prev"), ref.phi_prev)
+    print(f"[parity]   errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    bar = tol if tol is not None else TOL[prec]
+    for k, v in errs.items():
+        assert v <= bar, (label, prec, k, v)
+    s.close()
+    return errs
+
+
+# ---- the small configurations at full length ---------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config1_2d_full_length(lb, orc, prec):
+    compare(lb, orc, W.config1(), prec, 2000, fields=("phi", "U"), label="2-D 128^2 no flow")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16shift"])
+def test_2d_flow_inlet_outlet(lb, orc, prec):
+    p = W.sweep_instance(96, 0.3, 8.0, 0.025)
+    p["ny"] = 64
+    p["seed_c"] = (48.0, 32.0, 0.0)
+    compare(lb, orc, p, prec, 600, label="2-D flow open x")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_2d_flow_periodic(lb, orc, prec):
+    p = W.params(dim=2, nx=64, ny=48, flow=1, xbc=0, u_in=0.03, U0=0.3, seed_c=(32, 24, 0), seed_R=7.0)
+    compare(lb, orc, p, prec, 400, label="2-D flow periodic")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_3d_no_flow(lb, orc, prec):
+    p = W.scaled(W.config2(), 32, 32, 32, seed_R=6.0)
+    compare(lb, orc, p, prec, 300, fields=("phi", "U"), label="3-D no flow")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16shift"])
+def test_3d_flow_inlet_outlet(lb, orc, prec):
+    p = W.scaled(W.config3(), 48, 32, 32, seed_R=6.0)
+    compare(lb, orc, p, prec, 200, label="3-D flow open x")
+
+
+# ---- ragged tiles, tiny and degenerate grids -----------------------------------------------------
+
+@pytest.mark.parametrize("dim,dims,flow,xbc", [
+    (2, (37, 23, 1), 1, 1), (2, (37, 23, 1), 1, 0), (2, (3, 5, 1), 1, 1), (2, (1, 1, 1), 1, 0),
+    (2, (2, 1, 1), 0, 0), (3, (21, 13, 9), 1, 1), (3, (21, 13, 9), 0, 0), (3, (1, 1, 1), 1, 0),
+    (3, (3, 2, 5), 1, 1), (3, (70, 9, 6), 1, 0),
+])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ragged_and_tiny_grids(lb, orc, dim, dims, flow, xbc, prec):
+    nx, ny, nz = dims
+    c = (nx / 2, ny / 2, nz / 2 if dim == 3 else 0.0)
+    p = W.params(dim=dim, nx=nx, ny=ny, nz=nz, flow=flow, xbc=xbc, u_in=0.02, U0=0.3, seed_c=c,
+                 seed_R=max(1.5, min(nx, ny) / 3))
+    compare(lb, orc, p, prec, 50, label=f"ragged {dims}")
+
+
+# ---- full-size one-step checks in the benchmark's launch configuration ------------------------
+
+@pytest.mark.parametrize("cfg", ["config2", "config3"])
+def test_full_size_one_step_from_gpu_state(lb, orc, cfg):
+    """Run the full-size grid a while on the GPU (binary32), hand its state to the oracle, and
+    check one more step of every node against the oracle's step from the same state."""
+    p = getattr(W, cfg)()
+    print(f"[parity] full-size {cfg} one step", flush=True)
+    s = lb.Solver(p, "fp32")
+    s.step(30)
+    ref = orc.Sim(p, init=False)
+    ref.h[:] = s.read("raw_h")
+    ref.g[:] = s.read("raw_g")
+    if p["flow"]:
+        ref.f[:] = s.read("raw_f")
+    ref.phi_prev[:] = s.read("phi_prev")
+    s.step(1)
+    ref.step(1)
+    for name, a, b in (("h", s.read("raw_h"), ref.h), ("g", s.read("raw_g"), ref.g),
+                       ("phi_prev", s.read("phi_prev"), ref.phi_prev)) + (
+            (("f", s.read("raw_f"), ref.f),) if p["flow"] else ()):
+        # one binary32 step from the same state: rounding of a few ulp of the largest value
+        err = np.abs(a - b).max() / np.abs(b).max()
+        print(f"[parity]   {cfg} {name}: {err:.2e}", flush=True)
+        assert err < 2e-6, (cfg, name, err)
+    s.close()
+
+
+# ---- diagnostics -------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,flow", [(2, 0), (2, 1), (3, 1)])
+def test_measure_matches_oracle_on_same_state(lb, orc, dim, flow):
+    n = 64 if dim == 2 else 32
+    p = W.params(dim=dim, nx=n, ny=n, nz=1 if dim == 2 else n, flow=flow, xbc=flow, u_in=0.02, U0=0.3,
+                 seed_c=(n / 2, n / 2, n / 2 if dim == 3 else 0), seed_R=8.0 if dim == 2 else 6.0)
+    print(f"[parity] measure dim={dim} flow={flow}", flush=True)
+    ref = orc.Sim(p)
+    ref.step(300 if dim == 2 else 100)
+    s = lb.Solver(p, "fp64")
+    s.write("raw_h", ref.h)
+    s.write("raw_g", ref.g)
+    if flow:
+        s.write("raw_f", ref.f)
+    s.write("phi_prev", ref.phi_prev)
+    dirs = W.directions(16)
+    if dim == 3:
+        dirs = np.concatenate([dirs, [[0, 0, 1.0], [0, 0, -1.0], [0.6, 0, 0.8]]])
+    L, m = s.measure(dirs)
+    Lr, mr = ref.measure(dirs)
+    assert np.abs(L - Lr).max() < 1e-11, (L, Lr)
+    for k in ("sumU", "sumPhiPrev", "Vs", "Mprime"):
+        assert abs(m[k] - mr[k]) <= 1e-12 * max(1, abs(mr[k])), k
+    assert abs(m["umax"] - mr["umax"]) < 1e-14 and m["nonfinite"] == 0
+    s.close()
+
+
+def test_growth_rates_match_oracle_fit(lb, orc):
+    from oracle import growth
+    p = W.params(dim=2, nx=64, ny=64, U0=0.3, seed_c=(32, 32, 0), seed_R=6.0)
+    s = lb.Solver(p, "fp64")
+    dirs = W.directions(16)
+    t, Ls = [], []
+    for k in range(6):
+        L, _ = s.measure(dirs)
+        t.append(s.nstep)
+        Ls.append(L)
+        s.step(100)
+    G, R2, Ga = s.growth_rates(16)
+    Gr, R2r, Gar = growth.growth_rates(np.array(t, float), np.array(Ls))
+    assert np.abs(G - Gr).max() < 1e-12 and np.abs(R2 - R2r).max() < 1e-10 and abs(Ga - Gar) < 1e-12
+    assert (G > 0).all()  # a supersaturated seed grows in every direction
+    s.close()
+
+
+def test_solute_plus_solid_invariant_fp32(lb):
+    p = W.scaled(W.config2(), 64, 64, 64, seed_R=8.0)
+    s = lb.Solver(p, "fp32")
+    M0 = s.measure()[1]["Mprime"]
+    s.step(1000)
+    M1 = s.measure()[1]["Mprime"]
+    print(f"[parity] M' drift fp32 64^3 1000 steps: {abs(M1 - M0) / M0:.2e}", flush=True)
+    assert abs(M1 - M0) / M0 < 1e-6
+    s.close()
+
+
+# ---- state handling --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16shift"])
+def test_checkpoint_restart_and_determinism_bitwise(lb, prec):
+    p = W.scaled(W.config3(), 48, 32, 32, seed_R=6.0)
+    a = lb.Solver(p, prec)
+    a.step(40)
+    ck = {k: a.read(k, np.float64) for k in ("raw_h", "raw_g", "raw_f", "phi_prev")}
+    a.step(30)
+    b = lb.Solver(p, prec)
+    for k, v in ck.items():
+        b.write(k, v)
+    b.step(30)
+    c = lb.Solver(p, prec)
+    c.step(70)
+    for k in ("raw_h", "raw_g", "raw_f", "phi_prev"):
+        ra = a.read(k, np.float32)
+        assert np.array_equal(ra, b.read(k, np.float32)), k   # restart from a checkpoint
+        assert np.array_equal(ra, c.read(k, np.float32)), k   # a second run
+    for s in (a, b, c):
+        s.close()
+
+
+def test_nonfinite_is_reported(lb):
+    p = W.params(dim=2, nx=32, ny=32, seed_c=(16, 16, 0))
+    s = lb.Solver(p, "fp32")
+    h = s.read("raw_h")
+    h[0, 0, 3, 3] = np.nan
+    s.write("raw_h", h)
+    with pytest.raises(lb.LbcgError) as e:
+        s.measure()
+    assert e.value.status == "ENONFINITE"
+    with pytest.raises(lb.LbcgError) as e:
+        s.step(1)
+    assert e.value.status == "ENONFINITE"
+    s.close()
