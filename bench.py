@@ -1,0 +1,306 @@
+"""Benchmark of the coupled LB crystal-growth step on one MI355X.
+
+Headline workload: the 3-D forced-convection grid 192 x 128 x 128 (D3Q19 flow + D3Q7 phase field +
+D3Q7 solute, inlet/outlet in x, periodic y/z, seed R 12, U0 = U_in = 0.3), binary32, synthetic
+seeded input. One step = one coupled time step of all three lattices (one fused kernel); the
+timed loop also runs the diagnostics (binary64 reductions + ray-march along 16 directions) every
+100 steps. value = whole-job MLUPS (nodes x steps / time).
+
+Also reported: the fused kernel's roofline (algorithmic bytes per launch / HIP-event launch time,
+against the 8 TB/s HBM peak), HBM bytes from rocprofv3 counters when profiles/ holds them for the
+current kernel source, the binary16-shift variant, the no-flow 3-D grid, and the oracle timed on the
+host cores as a CPU baseline.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       python bench.py --profile-run            (short run for rocprofv3: step kernels + 1 GiB copy)
+       python bench.py --summarize-profiles DIR (rocprofv3 csv output -> profiles/*.md, traffic.json)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MEASURE_EVERY = 100
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def bytes_per_lup(p: dict, prec: str) -> int:
+    """Algorithmic HBM bytes per lattice update: every population read once and written once,
+    plus phi_prev read and written."""
+    qs = 5 if p["dim"] == 2 else 7
+    qf = (9 if p["dim"] == 2 else 19) if p["flow"] else 0
+    rs = 8 if prec == "fp64" else 4
+    fs = {"fp64": 8, "fp32": 4, "fp16shift": 2}[prec]
+    return 2 * (2 * qs * rs + qf * fs + rs)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("step.hpp", "lattice.hpp"):
+        with open(os.path.join(ROOT, "paper_2206_02145_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(name: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(name)
+    if not e or e.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def time_steps(s, steps: int, measure_every: int = 0, dirs=None):
+    """Run `steps` steps on the solver's stream between HIP events; returns milliseconds."""
+    import torch
+    st = s.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    done = 0
+    while done < steps:
+        n = min(measure_every, steps - done) if measure_every else steps
+        s.step(n)
+        done += n
+        if measure_every and done % measure_every == 0:
+            s.measure(dirs)  # synchronises; the event brackets it
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def gpu_case(name, p, prec, steps, warmup, with_measure):
+    import torch
+
+    from paper_2206_02145_amd import lbcg
+    from paper_2206_02145_amd import workloads as W
+    nodes = p["nx"] * p["ny"] * p["nz"]
+    s = lbcg.Solver(p, prec)
+    dirs = W.directions(16, p["dim"])
+    s.step(warmup)
+    torch.cuda.synchronize()
+    # the fused step kernel alone: launch-to-launch average on its stream
+    ms_kernel = time_steps(s, steps)
+    # whole job: steps plus the diagnostics every MEASURE_EVERY steps
+    ms_job = time_steps(s, steps, MEASURE_EVERY, dirs) if with_measure else ms_kernel
+    L, mass = s.measure(dirs)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    bpl = bytes_per_lup(p, prec)
+    t_launch = ms_kernel / steps * 1e-3
+    achieved = bpl * nodes / t_launch / 1e9
+    out = dict(name=name, nodes=nodes, steps=steps, ms_per_step=ms_job / steps,
+               mlups=nodes * steps / (ms_job * 1e-3) / 1e6,
+               kernel_ms=ms_kernel / steps, kernel_mlups=nodes / t_launch / 1e6,
+               bytes_per_lup=bpl, achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS,
+               crystal_mean_L=float(L.mean()), nonfinite=mass["nonfinite"])
+    log(f"{name}: {out['mlups']:.0f} MLUPS (job), kernel {out['kernel_ms']*1e3:.1f} us/step = "
+        f"{achieved:.0f} GB/s algorithmic ({out['frac']*100:.1f}% of {HBM_PEAK_GBS:.0f})")
+    return out
+
+
+def cpu_baseline(p, budget_s: float = 15.0):
+    """The oracle (FP64 C, OpenMP over rows) on the host cores: a bounded number of steps of the
+    same grid, reported in MLUPS."""
+    from oracle import oracle
+    oracle.build(force=False)
+    s = oracle.Sim(p)
+    t0 = time.time()
+    s.step(1)
+    t1 = time.time() - t0
+    n = max(1, int(budget_s / max(t1, 1e-3)))
+    t0 = time.time()
+    s.step(n)
+    dt = time.time() - t0
+    nodes = p["nx"] * p["ny"] * p["nz"]
+    return dict(value=nodes * n / dt / 1e6, unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{n} coupled steps of the full {p['nx']}x{p['ny']}x{p['nz']} grid after 1 warm-up "
+                       f"step ({dt:.1f} s, FP64)")
+
+
+PROFILE_STEPS = 20
+COPY_BYTES = 1 << 30
+
+
+def _kernel_tag(name: str) -> str:
+    """Short tag of a demangled kernel name."""
+    if "step_single<" in name:
+        args = name.split("step_single<", 1)[1].split(">", 1)[0].replace(" ", "")
+        dim, flow, real, fst = args.split(",")[:4]
+        prec = {"double": "fp64", "float": "fp32", "__half": "fp16shift"}[fst]
+        return f"step_{dim}d_{'flow' if flow == 'true' else 'noflow'}_{prec}"
+    if "copyBuffer" in name:
+        return "copy_1GiB"
+    return name.split("(")[0].split("<")[0].replace("void ", "").strip()
+
+
+def summarize_profiles(d: str):
+    """Turn the csv of three rocprofv3 runs of `bench.py --profile-run` (kernel trace + stats,
+    --pmc FETCH_SIZE, --pmc WRITE_SIZE) into profiles/step_3d_flow_c3.md and profiles/traffic.json.
+    Counter values are KiB per dispatch; each is scaled by what the same counter reads for the
+    1 GiB copy (bytes known)."""
+    import csv
+    import statistics as st
+
+    def rows(sub, fname):
+        with open(os.path.join(d, sub, fname)) as fh:
+            return list(csv.DictReader(fh))
+
+    stats = {}
+    for r in rows("prof_kt", "run_kernel_trace.csv"):
+        stats.setdefault(_kernel_tag(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    counters = {}
+    for sub, cname in (("prof_fetch", "FETCH_SIZE"), ("prof_write", "WRITE_SIZE")):
+        for r in rows(sub, "run_counter_collection.csv"):
+            if r["Counter_Name"] != cname:
+                continue
+            counters.setdefault((_kernel_tag(r["Kernel_Name"]), cname), []).append(float(r["Counter_Value"]))
+    # the copy reads and writes 1 GiB: factor = true KiB / counted KiB
+    cal = {}
+    cal["FETCH_SIZE"] = (COPY_BYTES / 1024) / st.mean(counters[("copy_1GiB", "FETCH_SIZE")])
+    cal["WRITE_SIZE"] = (COPY_BYTES / 1024) / st.mean(counters[("copy_1GiB", "WRITE_SIZE")])
+    from paper_2206_02145_amd import workloads as W
+    p3 = W.config3()
+    nodes = p3["nx"] * p3["ny"] * p3["nz"]
+    traffic = {}
+    lines = ["# rocprofv3 summary: fused coupled step, 3-D 192x128x128 with flow (C3)", "",
+             "Commands (from the repository root, TMPDIR=/tmp):", "",
+             "    rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_kt -o run -- python3 bench.py --profile-run",
+             "    rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o run -- python3 bench.py --profile-run",
+             "    rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o run -- python3 bench.py --profile-run",
+             "    python3 bench.py --summarize-profiles gpurun_out", "",
+             f"Counter calibration on a 1 GiB device copy: FETCH_SIZE x {cal['FETCH_SIZE']:.3f}, "
+             f"WRITE_SIZE x {cal['WRITE_SIZE']:.3f} (true bytes / counted bytes).", "",
+             "| kernel | calls | avg us | min us | max us | read MB | write MB | algorithmic MB | measured / algorithmic | GB/s (measured bytes) |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    for tag in sorted(stats):
+        ts = stats[tag]
+        fe = counters.get((tag, "FETCH_SIZE"))
+        wr = counters.get((tag, "WRITE_SIZE"))
+        rd_mb = st.mean(fe) * 1024 * cal["FETCH_SIZE"] / 1e6 if fe else float("nan")
+        wr_mb = st.mean(wr) * 1024 * cal["WRITE_SIZE"] / 1e6 if wr else float("nan")
+        alg = ""
+        ratio = ""
+        if tag.startswith("step_3d_flow"):
+            prec = tag.rsplit("_", 1)[1]
+            alg_b = bytes_per_lup(p3, prec) * nodes
+            alg = f"{alg_b / 1e6:.1f}"
+            ratio = f"{(rd_mb + wr_mb) * 1e6 / alg_b:.3f}"
+            traffic[tag] = {"bytes_per_launch": round((rd_mb + wr_mb) * 1e6),
+                            "read_bytes": round(rd_mb * 1e6), "write_bytes": round(wr_mb * 1e6),
+                            "avg_us": round(st.mean(ts), 2), "kernel_source_hash": kernel_source_hash()}
+        elif tag == "copy_1GiB":
+            alg = f"{2 * COPY_BYTES / 1e6:.1f}"
+        gbs = (rd_mb + wr_mb) * 1e6 / (st.mean(ts) * 1e-6) / 1e9 if fe and wr else float("nan")
+        lines.append(f"| {tag} | {len(ts)} | {st.mean(ts):.1f} | {min(ts):.1f} | {max(ts):.1f} | "
+                     f"{rd_mb:.1f} | {wr_mb:.1f} | {alg} | {ratio} | {gbs:.0f} |")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", "step_3d_flow_c3.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(traffic, fh, indent=1)
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="a short run of the headline kernel and a 1 GiB copy, for rocprofv3")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="summarise rocprofv3 csv output under DIR into profiles/")
+    args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this solver runs on a "
+              f"single MI355X; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    from paper_2206_02145_amd import lbcg
+    from paper_2206_02145_amd import workloads as W
+    lbcg.lib()
+
+    p3 = W.config3()
+    if args.profile_run:
+        s = lbcg.Solver(p3, "fp32")
+        s.step(20)
+        s16 = lbcg.Solver(W.config3(), "fp16shift")
+        s16.step(20)
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)  # 1 GiB read + 1 GiB write, the counter calibration
+        torch.cuda.synchronize()
+        log("profile run done")
+        return
+
+    head = gpu_case("3-D flow 192x128x128 fp32", p3, "fp32", args.steps, args.warmup, True)
+    f16 = gpu_case("3-D flow 192x128x128 fp16shift", p3, "fp16shift", args.steps, args.warmup, False)
+    c2 = gpu_case("3-D no-flow 128^3 fp32", W.config2(), "fp32", args.steps, args.warmup, False)
+    cpu = None if args.no_cpu else cpu_baseline(p3)
+    if cpu:
+        log(f"cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads ({cpu['sample']})")
+
+    traffic = counter_traffic("step_3d_flow_fp32")
+    f16["traffic"] = counter_traffic("step_3d_flow_fp16shift")
+    rec = {
+        "metric": "coupled-LB MLUPS & HBM-roofline %; sweep runs/s batched vs plain at 1e-4 err",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded tanh seed, uniform supersaturation, inlet flow)",
+        "config": {"workload": "3-D coupled phase-field/solute/flow LB, 192x128x128, D3Q7+D3Q7+D3Q19, "
+                               "inlet u=0.02 at x-, outlet x+, periodic y/z, seed R=12, U0=U_in=0.3",
+                   "nodes": head["nodes"], "diagnostics_every": MEASURE_EVERY, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(head["frac"], 4),
+                     "traffic": traffic,
+                     "kernel": "step_single<3, flow, float, float, 32, 4, 4>",
+                     "bytes_per_lup": head["bytes_per_lup"], "kernel_us": round(head["kernel_ms"] * 1e3, 2)},
+        "cpu_baseline": cpu,
+        "variants": {
+            "fp16shift_flow": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in f16.items()},
+            "no_flow_128cube": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c2.items()},
+        },
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()
