@@ -144,6 +144,23 @@ lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* 
  * taken with the same ndirs (ESTATE otherwise). Any output may be NULL. */
 lbcg_status lbcg_growth_rates(lbcg_handle* h, double* G_out, double* R2_out, double* G_avg_out);
 
+/* Step-kernel variants: the tilings the library can run for this solver (z-marching over full
+ * rows or 3-D blocks, of several shapes). Every variant computes the same update bit for bit;
+ * they differ only in speed. Variant 0 is the default. */
+int lbcg_variant_count(const lbcg_handle* h);   /* -1 for a NULL handle */
+int lbcg_variant_current(const lbcg_handle* h); /* -1 for a NULL handle */
+lbcg_status lbcg_variant_name(const lbcg_handle* h, int idx, char* buf, size_t buflen);
+lbcg_status lbcg_variant_select(lbcg_handle* h, int idx);
+
+/* Mean launch time (microseconds, HIP events on the handle's stream) of `launches` launches of
+ * variant idx on the current state, which is left unchanged (phi_prev is saved in the staging
+ * area and restored). Synchronises. */
+lbcg_status lbcg_variant_time(lbcg_handle* h, int idx, int launches, double* us);
+
+/* Time every variant as lbcg_variant_time does, select the fastest, and return its index and
+ * time (either output may be NULL). The state is unchanged. Synchronises. */
+lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_us);
+
 /* Release the host handle (the workspace stays the caller's). NULL is accepted. */
 lbcg_status lbcg_destroy(lbcg_handle* h);
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lattice.hpp"
+#include "mem.hpp"
 #include "step.hpp"
 
 namespace lbcg {
@@ -22,32 +23,32 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev I, int par, SeedArgs 
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
     const long long N = I.N;
-    real* h = static_cast<real*>(I.h[par]);
-    real* g = static_cast<real*>(I.g[par]);
-    real* pp = static_cast<real*>(I.phi_prev);
+    const Planes<real> h(I.h[par], N), g(I.g[par], N), pp(I.phi_prev, N);
+    const Planes<fst> f(I.f[par], N);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % I.nx);
         const long long r = i / I.nx;
         const int y = (int)(r % I.ny);
         const int z = (int)(r / I.ny);
+        const unsigned row = (unsigned)(i - x);
         const double dx = x - s.cx, dy = y - s.cy, dz = (DIM == 3) ? z - s.cz : 0.0;
         const double d = sqrt(dx * dx + dy * dy + dz * dz);
         const double phi0 = tanh((s.R - d) / (sqrt(2.0) * s.W0));
-        pp[i] = (real)(phi0 + 1.0);
+        pp.st(0, (unsigned)i, (real)(phi0 + 1.0));
 #pragma unroll
         for (int a = 0; a < S::Q; a++) {
-            h[a * N + i] = (real)(S::w(a) * (phi0 + 1.0));  // h + w
-            g[a * N + i] = (real)0;                         // g - w U0
+            const unsigned m = row + xmem(x, S::c(a, 0), I.nx);
+            h.st(a, m, (real)(S::w(a) * (phi0 + 1.0)));  // h + w
+            g.st(a, m, (real)0);                         // g - w U0
         }
         if constexpr (FLOW) {
-            fst* f = static_cast<fst*>(I.f[par]);
             const double ux = s.u_in * 0.5 * (1.0 - phi0);
 #pragma unroll
             for (int a = 0; a < V::Q; a++) {
                 const double cu = V::c(a, 0) * ux;
                 const double dev = V::w(a) * (3.0 * cu + 4.5 * cu * cu - 1.5 * ux * ux);  // f_eq - w
-                Store<real, fst>::st_(f, a * N + i, (real)dev);
+                f.st(a, row + xmem(x, V::c(a, 0), I.nx), (real)dev);
             }
         }
     }
@@ -60,23 +61,25 @@ __device__ inline void node_moments(const InstDev& I, int par, long long i, real
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
     const long long N = I.N;
-    const real* h = static_cast<const real*>(I.h[par]);
-    const real* g = static_cast<const real*>(I.g[par]);
+    const Planes<real> h(I.h[par], N), g(I.g[par], N);
+    const int x = (int)(i % I.nx);
+    const unsigned row = (unsigned)(i - x);
     psi = 0;
     Ut = 0;
 #pragma unroll
     for (int a = 0; a < S::Q; a++) {
-        psi += h[a * N + i];
-        Ut += g[a * N + i];
+        const unsigned m = row + xmem(x, S::c(a, 0), I.nx);
+        psi += h.template ld<real>(a, m);
+        Ut += g.template ld<real>(a, m);
     }
     rho = 1;
     usx = usy = usz = 0;
     if constexpr (FLOW) {
-        const fst* f = static_cast<const fst*>(I.f[par]);
+        const Planes<fst> f(I.f[par], N);
         real drho = 0, mx = 0, my = 0, mz = 0;
 #pragma unroll
         for (int a = 0; a < V::Q; a++) {
-            const real fa = Store<real, fst>::ld(f, a * N + i);
+            const real fa = f.template ld<real>(a, row + xmem(x, V::c(a, 0), I.nx));
             drho += fa;
             if (V::c(a, 0)) mx += (real)V::c(a, 0) * fa;
             if (V::c(a, 1)) my += (real)V::c(a, 1) * fa;
@@ -101,7 +104,7 @@ __global__ __launch_bounds__(256) void field_kernel(InstDev I, int par, int fiel
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
          i += (long long)gridDim.x * blockDim.x) {
         if (field == 6) {
-            out[i] = (out_t)((double)pp[i] - 1.0);
+            out[i] = (out_t)((double)pp[i] - 1.0);  // psi_prev = phi_prev + 1 (no column shift)
             continue;
         }
         real psi, Ut, rho, ux, uy, uz;
@@ -112,20 +115,29 @@ __global__ __launch_bounds__(256) void field_kernel(InstDev I, int par, int fiel
     }
 }
 
-// One stored plane to out, decoded: value = stored deviation + shift (h: -w, g: w U0, f: w).
+// One stored plane to out, decoded to the plain layout: value(x) = stored(column xmem(x, cx)) + shift
+// (h: -w, g: w U0, f: w).
 template <typename real, typename st, typename out_t>
-__global__ __launch_bounds__(256) void raw_read_kernel(const st* src, long long n, double shift, out_t* out) {
+__global__ __launch_bounds__(256) void raw_read_kernel(const st* src, long long n, int nx, int cx, double shift,
+                                                       out_t* out) {
+    const Planes<st> P(src, n);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        out[i] = (out_t)((double)Store<real, st>::ld(src, i) + shift);
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        out[i] = (out_t)((double)P.template ld<real>(0, (unsigned)(i - x) + xmem(x, cx, nx)) + shift);
+    }
 }
 
-// One plane from in, encoded: stored = value - shift, rounded once to the storage type.
+// One plane from the plain layout, encoded: stored(column xmem(x, cx)) = value(x) - shift, rounded once.
 template <typename real, typename st, typename in_t>
-__global__ __launch_bounds__(256) void raw_write_kernel(st* dst, long long n, double shift, const in_t* in) {
+__global__ __launch_bounds__(256) void raw_write_kernel(st* dst, long long n, int nx, int cx, double shift,
+                                                        const in_t* in) {
+    const Planes<st> P(dst, n);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        Store<real, st>::st_(dst, i, (real)((double)in[i] - shift));
+         i += (long long)gridDim.x * blockDim.x) {
+        const int x = (int)(i % nx);
+        P.st(0, (unsigned)(i - x) + xmem(x, cx, nx), (real)((double)in[i] - shift));
+    }
 }
 
 // ---- reductions (binary64 accumulation) ----
@@ -194,10 +206,10 @@ __global__ __launch_bounds__(64) void reduce_final(const double* partials, int n
 template <int DIM, typename real>
 __device__ inline double phi_node(const InstDev& I, const real* h, int x, int y, int z) {
     using S = typename Lattices<DIM>::S;
-    const long long i = ((long long)z * I.ny + y) * I.nx + x;
+    const long long row = ((long long)z * I.ny + y) * I.nx;
     double psi = 0;
 #pragma unroll
-    for (int a = 0; a < S::Q; a++) psi += (double)h[a * I.N + i];
+    for (int a = 0; a < S::Q; a++) psi += (double)h[a * I.N + row + xmem(x, S::c(a, 0), I.nx)];
     return psi - 1.0;
 }
 

@@ -16,6 +16,7 @@
 #include "../../include/lbcg.h"
 #include "diag.hpp"
 #include "lattice.hpp"
+#include "march.hpp"
 #include "step.hpp"
 
 using namespace lbcg;
@@ -75,8 +76,8 @@ void validate(const lbcg_params* p) {
     if (p->xbc == LBCG_INFLOW_OUTFLOW && p->nx < 3) throw Error(LBCG_EINVAL, "open x faces need nx >= 3");
     if (p->reserved != 0) throw Error(LBCG_EINVAL, "reserved must be 0");
     const double N = (double)p->nx * p->ny * p->nz;
-    if (N * qf_of(p->dim) > 4.0e18 / 8 || (double)p->nx * p->ny > 2.0e9)
-        throw Error(LBCG_EINVAL, "grid too large");
+    if (N >= 536870912.0)  // each population plane is addressed with 32-bit byte offsets
+        throw Error(LBCG_EINVAL, "grid too large (at most 2^29 - 1 nodes)");
     const double vals[] = {p->W0, p->tau0, p->lambda, p->D, p->eps_aniso, p->nu, p->h_drag,
                            p->u_inlet, p->U0, p->U_inlet, p->seed_center[0], p->seed_center[1],
                            p->seed_center[2], p->seed_radius, p->grad_eps2};
@@ -117,16 +118,25 @@ Layout layout_of(const lbcg_params* p) {
     return L;
 }
 
-InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, int TX, int TY, int TZ) {
+// Tiling of the step kernel: a TX x TY x TZ block, or (march) TY full rows x TZ planes.
+struct Tiling {
+    bool march;
+    int TX, TY, TZ;
+    bool prefetch;  // own populations loaded before the halo barrier
+    int aux;        // store cache policy
+};
+
+InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling& T) {
     InstDev I{};
     I.nx = p->nx;
     I.ny = p->ny;
     I.nz = p->nz;
     I.xopen = p->xbc == LBCG_INFLOW_OUTFLOW;
-    I.tiles_x = (p->nx + TX - 1) / TX;
-    I.tiles_y = (p->ny + TY - 1) / TY;
-    I.tiles_z = p->dim == 3 ? (p->nz + TZ - 1) / TZ : 1;
+    I.tiles_x = T.march ? 1 : (p->nx + T.TX - 1) / T.TX;
+    I.tiles_y = (p->ny + T.TY - 1) / T.TY;
+    I.tiles_z = p->dim == 3 ? (p->nz + T.TZ - 1) / T.TZ : 1;
     I.tile_begin = 0;
+    I.zc = T.TZ;
     I.N = (long long)p->nx * p->ny * p->nz;
     for (int k = 0; k < 2; k++) {
         I.h[k] = ws + L.h[k];
@@ -148,9 +158,9 @@ InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, int TX, int T
     return I;
 }
 
-// ---- kernel dispatch per (dim, flow, precision) ----
+// ---- kernel dispatch per (dim, flow, precision, row length) ----
 struct Ops {
-    int TX, TY, TZ;
+    Tiling tiling;
     void (*step)(const InstDev&, int par, hipStream_t);
     void (*init)(const InstDev&, int par, const SeedArgs&, hipStream_t);
     void (*field)(const InstDev&, int par, int field, void* out, int dtype, hipStream_t);
@@ -170,6 +180,16 @@ double plane_shift(const lbcg_params& p, int field, int a) {
     }
 }
 
+// x-velocity of plane a of a population array (its column shift in the stored layout).
+int plane_cx(const lbcg_params& p, int field, int a) {
+    switch (field) {
+        case LBCG_FIELD_RAW_H:
+        case LBCG_FIELD_RAW_G: return p.dim == 2 ? D2Q5::c(a, 0) : D3Q7::c(a, 0);
+        case LBCG_FIELD_RAW_F: return p.dim == 2 ? D2Q9::c(a, 0) : D3Q19::c(a, 0);
+        default: return 0;  // PHI_PREV
+    }
+}
+
 int grid_for(long long n, int threads, int cap) {
     long long b = (n + threads - 1) / threads;
     if (b > cap) b = cap;
@@ -177,13 +197,9 @@ int grid_for(long long n, int threads, int cap) {
     return (int)b;
 }
 
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ>
-struct OpsImpl {
-    static void step(const InstDev& I, int par, hipStream_t s) {
-        const int nblocks = I.tiles_x * I.tiles_y * I.tiles_z;
-        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ>), dim3(nblocks), dim3(TX * TY * TZ),
-                           0, s, I, par);
-    }
+// Everything except the step kernel: shared by every tiling of one (dim, flow, precision).
+template <int DIM, bool FLOW, typename real, typename fst>
+struct CommonOps {
     static void init(const InstDev& I, int par, const SeedArgs& a, hipStream_t s) {
         hipLaunchKernelGGL((init_kernel<DIM, FLOW, real, fst>), dim3(grid_for(I.N, 256, 65536)), dim3(256),
                            0, s, I, par, a);
@@ -207,28 +223,166 @@ struct OpsImpl {
         hipLaunchKernelGGL((raymarch_kernel<DIM, real>), dim3(ndirs), dim3(64), 0, s, I, par, dirs, c[0], c[1],
                            c[2], out);
     }
-    static Ops ops() { return Ops{TX, TY, TZ, step, init, field, reduce, ray}; }
 };
 
-const Ops& ops_for(int dim, int flow, int prec) {
-    // 2-D tiles 64 x 4; 3-D tiles 32 x 4 x 4 (binary32) and 16 x 4 x 4 (binary64, LDS size).
-    static const Ops t2_nf_64 = OpsImpl<2, false, double, double, 64, 4, 1>::ops();
-    static const Ops t2_nf_32 = OpsImpl<2, false, float, float, 64, 4, 1>::ops();
-    static const Ops t2_f_64 = OpsImpl<2, true, double, double, 64, 4, 1>::ops();
-    static const Ops t2_f_32 = OpsImpl<2, true, float, float, 64, 4, 1>::ops();
-    static const Ops t2_f_16 = OpsImpl<2, true, float, __half, 64, 4, 1>::ops();
-    static const Ops t3_nf_64 = OpsImpl<3, false, double, double, 16, 4, 4>::ops();
-    static const Ops t3_nf_32 = OpsImpl<3, false, float, float, 32, 4, 4>::ops();
-    static const Ops t3_f_64 = OpsImpl<3, true, double, double, 16, 4, 4>::ops();
-    static const Ops t3_f_32 = OpsImpl<3, true, float, float, 32, 4, 4>::ops();
-    static const Ops t3_f_16 = OpsImpl<3, true, float, __half, 32, 4, 4>::ops();
-    if (dim == 2) {
-        if (!flow) return prec == LBCG_FP64 ? t2_nf_64 : t2_nf_32;
-        return prec == LBCG_FP64 ? t2_f_64 : (prec == LBCG_FP32 ? t2_f_32 : t2_f_16);
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0>
+struct BlockOps : CommonOps<DIM, FLOW, real, fst> {
+    using C = CommonOps<DIM, FLOW, real, fst>;
+    static void step(const InstDev& I, int par, hipStream_t s) {
+        const int nblocks = I.tiles_x * I.tiles_y * I.tiles_z;
+        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX>), dim3(nblocks),
+                           dim3(TX * TY * TZ), 0, s, I, par);
     }
-    if (!flow) return prec == LBCG_FP64 ? t3_nf_64 : t3_nf_32;
-    return prec == LBCG_FP64 ? t3_f_64 : (prec == LBCG_FP32 ? t3_f_32 : t3_f_16);
+    static Ops ops() { return Ops{Tiling{false, TX, TY, TZ, PF, AUX}, step, C::init, C::field, C::reduce, C::ray}; }
+};
+
+template <bool FLOW, typename real, typename fst, int NW, int TY>
+struct MarchOps : CommonOps<3, FLOW, real, fst> {
+    using C = CommonOps<3, FLOW, real, fst>;
+    static void step(const InstDev& I, int par, hipStream_t s) {
+        const int nblocks = I.tiles_y * I.tiles_z;
+        hipLaunchKernelGGL((march3d_single<FLOW, real, fst, NW, TY>), dim3(nblocks), dim3(64 * NW * TY), 0, s,
+                           I, par, I.zc);
+    }
+    static Ops ops() { return Ops{Tiling{true, 64 * NW, TY, 16, true, 0}, step, C::init, C::field, C::reduce, C::ray}; }
+};
+
+// A variant = kernel instantiation + tiling (the z-marching kernel takes its plane count at run time).
+struct Variant {
+    const Ops* ops;
+    Tiling tiling;
+};
+
+template <bool FLOW, typename real, typename fst, int TY>
+const Ops* march_ops(int nx) {
+    static const Ops m1 = MarchOps<FLOW, real, fst, 1, TY>::ops();
+    static const Ops m2 = MarchOps<FLOW, real, fst, 2, TY>::ops();
+    static const Ops m3 = MarchOps<FLOW, real, fst, 3, TY>::ops();
+    static const Ops m4 = MarchOps<FLOW, real, fst, 4, TY>::ops();
+    return nx <= 64 ? &m1 : nx <= 128 ? &m2 : nx <= 192 ? &m3 : &m4;
 }
+
+constexpr int MARCH_MAX_NX = 256;
+
+template <int DIM, bool FLOW, typename real, typename fst>
+void block_variants(std::vector<Variant>& v) {
+    auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
+    if constexpr (DIM == 2) {
+        static const Ops a = BlockOps<2, FLOW, real, fst, 64, 4, 1, true>::ops();
+        static const Ops b = BlockOps<2, FLOW, real, fst, 64, 4, 1>::ops();
+        static const Ops c = BlockOps<2, FLOW, real, fst, 64, 2, 1, true>::ops();
+        static const Ops d = BlockOps<2, FLOW, real, fst, 64, 8, 1, true>::ops();
+        static const Ops e = BlockOps<2, FLOW, real, fst, 128, 2, 1, true>::ops();
+        for (const Ops* o : {&a, &b, &c, &d, &e}) add(*o);
+    } else if constexpr (sizeof(real) == 8) {
+        static const Ops a = BlockOps<3, FLOW, real, fst, 16, 4, 4>::ops();
+        static const Ops b = BlockOps<3, FLOW, real, fst, 32, 2, 4, true>::ops();
+        add(a);
+        add(b);
+    } else {
+        static const Ops a0 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 0>::ops();
+        static const Ops a1 = BlockOps<3, FLOW, real, fst, 64, 2, 4, true, 0>::ops();
+        static const Ops a2 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2>::ops();
+        static const Ops a3 = BlockOps<3, FLOW, real, fst, 64, 2, 4, true, 2>::ops();
+        static const Ops b0 = BlockOps<3, FLOW, real, fst, 64, 4, 2, true>::ops();
+        static const Ops b1 = BlockOps<3, FLOW, real, fst, 64, 1, 8, true>::ops();
+        static const Ops b2 = BlockOps<3, FLOW, real, fst, 64, 4, 4, true>::ops();
+        static const Ops b3 = BlockOps<3, FLOW, real, fst, 64, 2, 2, true>::ops();
+        static const Ops c0 = BlockOps<3, FLOW, real, fst, 32, 8, 2>::ops();
+        static const Ops c1 = BlockOps<3, FLOW, real, fst, 32, 8, 2, true>::ops();
+        static const Ops c2 = BlockOps<3, FLOW, real, fst, 32, 4, 4, true>::ops();
+        // first = default: the fastest on the 3-D flow grids measured on MI355X
+        for (const Ops* o : {&a2, &a3, &a0, &a1, &b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
+    }
+}
+
+template <int DIM, bool FLOW, typename real, typename fst>
+std::vector<Variant> variants_of(int nx) {
+    std::vector<Variant> v;
+    block_variants<DIM, FLOW, real, fst>(v);
+    if constexpr (DIM == 3) {
+        if (nx <= MARCH_MAX_NX) {
+            // z-marching kernel first: the default for 3-D grids with rows of up to 256 nodes
+            const int zcs[] = {8, 16, 4, 32};
+            for (int zc : zcs) {
+                const Ops* o = march_ops<FLOW, real, fst, 2>(nx);
+                v.push_back({o, Tiling{true, o->tiling.TX, 2, zc, true, 0}});
+            }
+            for (int zc : zcs) {
+                const Ops* o = march_ops<FLOW, real, fst, 1>(nx);
+                v.push_back({o, Tiling{true, o->tiling.TX, 1, zc, true, 0}});
+            }
+            if constexpr (sizeof(real) == 4) {
+                for (int zc : zcs) {
+                    const Ops* o = march_ops<FLOW, real, fst, 4>(nx);
+                    v.push_back({o, Tiling{true, o->tiling.TX, 4, zc, true, 0}});
+                }
+            }
+        }
+    }
+    return v;
+}
+
+std::vector<Variant> variants_for(int dim, int flow, int prec, int nx) {
+    if (dim == 2) {
+        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx) : variants_of<2, false, float, float>(nx);
+        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx)
+               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx)
+                                   : variants_of<2, true, float, __half>(nx);
+    }
+    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx) : variants_of<3, false, float, float>(nx);
+    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx)
+           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx)
+                               : variants_of<3, true, float, __half>(nx);
+}
+
+std::string variant_name(const Variant& v) {
+    const Tiling& t = v.tiling;
+    char buf[96];
+    if (t.march)
+        std::snprintf(buf, sizeof buf, "march rows=%d x %d planes (row %d)", t.TY, t.TZ, t.TX);
+    else
+        std::snprintf(buf, sizeof buf, "block %dx%dx%d%s%s", t.TX, t.TY, t.TZ, t.prefetch ? " prefetch" : "",
+                      t.aux ? " nt-stores" : "");
+    return buf;
+}
+
+// Plane a of a raw array (base = the array) into out, decoded to the plain layout.
+template <typename real, typename st>
+void raw_read_t(const lbcg_params& p, const void* base, int field, int a, long long N, void* out, int dtype,
+                hipStream_t s) {
+    const st* src = (const st*)base + (size_t)a * N;
+    const int nb = grid_for(N, 256, 65536);
+    const int cx = plane_cx(p, field, a);
+    const double sh = plane_shift(p, field, a);
+    if (dtype == LBCG_DTYPE_F64)
+        hipLaunchKernelGGL((raw_read_kernel<real, st, double>), dim3(nb), dim3(256), 0, s, src, N, p.nx, cx, sh,
+                           (double*)out);
+    else
+        hipLaunchKernelGGL((raw_read_kernel<real, st, float>), dim3(nb), dim3(256), 0, s, src, N, p.nx, cx, sh,
+                           (float*)out);
+}
+
+template <typename real, typename st>
+void raw_write_t(const lbcg_params& p, void* base, int field, int a, long long N, const void* in, int dtype,
+                 hipStream_t s) {
+    st* dst = (st*)base + (size_t)a * N;
+    const int nb = grid_for(N, 256, 65536);
+    const int cx = plane_cx(p, field, a);
+    const double sh = plane_shift(p, field, a);
+    if (dtype == LBCG_DTYPE_F64)
+        hipLaunchKernelGGL((raw_write_kernel<real, st, double>), dim3(nb), dim3(256), 0, s, dst, N, p.nx, cx, sh,
+                           (const double*)in);
+    else
+        hipLaunchKernelGGL((raw_write_kernel<real, st, float>), dim3(nb), dim3(256), 0, s, dst, N, p.nx, cx, sh,
+                           (const float*)in);
+}
+
+int storage_kind(const lbcg_params& p, int field) {  // 0 double, 1 float, 2 half
+    if (p.precision == LBCG_FP64) return 0;
+    return (field == LBCG_FIELD_RAW_F && p.precision == LBCG_FP32_F16SHIFT) ? 2 : 1;
+}
+
 
 }  // namespace
 
@@ -237,6 +391,8 @@ struct lbcg_handle {
     Layout L;
     char* ws;
     hipStream_t stream;
+    std::vector<Variant> variants;
+    int variant;
     const Ops* ops;
     InstDev inst;
     int par;
@@ -276,8 +432,10 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
         hdl->L = L;
         hdl->ws = (char*)dev_workspace;
         hdl->stream = (hipStream_t)hip_stream;
-        hdl->ops = &ops_for(p->dim, p->flow, p->precision);
-        hdl->inst = make_inst(p, hdl->ws, L, hdl->ops->TX, hdl->ops->TY, hdl->ops->TZ);
+        hdl->variants = variants_for(p->dim, p->flow, p->precision, p->nx);
+        hdl->variant = 0;
+        hdl->ops = hdl->variants[0].ops;
+        hdl->inst = make_inst(p, hdl->ws, L, hdl->variants[0].tiling);
         hdl->par = 0;
         hdl->nstep = 0;
         hdl->red_blocks = grid_for(hdl->inst.N, RED_THREADS, RED_BLOCKS);
@@ -334,36 +492,13 @@ lbcg_status lbcg_read_field(lbcg_handle* h, int field, void* dst, size_t dst_byt
             if (field < LBCG_FIELD_RAW_H) {
                 h->ops->field(h->inst, h->par, field, tgt, dst_dtype, h->stream);
             } else {
-                const int nb = grid_for(N, 256, 65536);
-                const bool isF = field == LBCG_FIELD_RAW_F;
-                const double w = plane_shift(p, field, a);
                 const void* base = field == LBCG_FIELD_RAW_H ? h->inst.h[h->par]
                                    : field == LBCG_FIELD_RAW_G ? h->inst.g[h->par]
                                                                : h->inst.f[h->par];
-                if (p.precision == LBCG_FP64) {
-                    const double* src = (const double*)base + (size_t)a * N;
-                    if (dst_dtype == LBCG_DTYPE_F64)
-                        hipLaunchKernelGGL((raw_read_kernel<double, double, double>), dim3(nb), dim3(256), 0, h->stream,
-                                           src, N, w, (double*)tgt);
-                    else
-                        hipLaunchKernelGGL((raw_read_kernel<double, double, float>), dim3(nb), dim3(256), 0, h->stream,
-                                           src, N, w, (float*)tgt);
-                } else if (p.precision == LBCG_FP32 || !isF) {
-                    const float* src = (const float*)base + (size_t)a * N;
-                    if (dst_dtype == LBCG_DTYPE_F64)
-                        hipLaunchKernelGGL((raw_read_kernel<float, float, double>), dim3(nb), dim3(256), 0, h->stream,
-                                           src, N, w, (double*)tgt);
-                    else
-                        hipLaunchKernelGGL((raw_read_kernel<float, float, float>), dim3(nb), dim3(256), 0, h->stream,
-                                           src, N, w, (float*)tgt);
-                } else {
-                    const __half* src = (const __half*)base + (size_t)a * N;
-                    if (dst_dtype == LBCG_DTYPE_F64)
-                        hipLaunchKernelGGL((raw_read_kernel<float, __half, double>), dim3(nb), dim3(256), 0, h->stream,
-                                           src, N, w, (double*)tgt);
-                    else
-                        hipLaunchKernelGGL((raw_read_kernel<float, __half, float>), dim3(nb), dim3(256), 0, h->stream,
-                                           src, N, w, (float*)tgt);
+                switch (storage_kind(p, field)) {
+                    case 0: raw_read_t<double, double>(p, base, field, a, N, tgt, dst_dtype, h->stream); break;
+                    case 1: raw_read_t<float, float>(p, base, field, a, N, tgt, dst_dtype, h->stream); break;
+                    default: raw_read_t<float, __half>(p, base, field, a, N, tgt, dst_dtype, h->stream); break;
                 }
             }
             HIPCHK(hipGetLastError());
@@ -392,43 +527,20 @@ lbcg_status lbcg_write_field(lbcg_handle* h, int field, const void* src, size_t 
                                                                                  : 1;
         if (src_bytes < (size_t)planes * N * es) throw Error(LBCG_ENOMEM, "source too small");
         void* stage = h->ws + h->L.staging;
-        const int nb = grid_for(N, 256, 65536);
         for (int a = 0; a < planes; a++) {
             const void* in = (const char*)src + (size_t)a * N * es;
             if (!src_on_device) {
                 HIPCHK(hipMemcpyAsync(stage, in, N * es, hipMemcpyHostToDevice, h->stream));
                 in = stage;
             }
-            const bool isF = field == LBCG_FIELD_RAW_F;
-            const double w = plane_shift(p, field, a);
             void* base = field == LBCG_FIELD_RAW_H   ? h->inst.h[h->par]
                          : field == LBCG_FIELD_RAW_G ? h->inst.g[h->par]
                          : field == LBCG_FIELD_RAW_F ? h->inst.f[h->par]
                                                      : h->inst.phi_prev;
-            if (p.precision == LBCG_FP64) {
-                double* d = (double*)base + (size_t)a * N;
-                if (src_dtype == LBCG_DTYPE_F64)
-                    hipLaunchKernelGGL((raw_write_kernel<double, double, double>), dim3(nb), dim3(256), 0, h->stream, d,
-                                       N, w, (const double*)in);
-                else
-                    hipLaunchKernelGGL((raw_write_kernel<double, double, float>), dim3(nb), dim3(256), 0, h->stream, d,
-                                       N, w, (const float*)in);
-            } else if (p.precision == LBCG_FP32 || !isF) {
-                float* d = (float*)base + (size_t)a * N;
-                if (src_dtype == LBCG_DTYPE_F64)
-                    hipLaunchKernelGGL((raw_write_kernel<float, float, double>), dim3(nb), dim3(256), 0, h->stream, d, N,
-                                       w, (const double*)in);
-                else
-                    hipLaunchKernelGGL((raw_write_kernel<float, float, float>), dim3(nb), dim3(256), 0, h->stream, d, N,
-                                       w, (const float*)in);
-            } else {
-                __half* d = (__half*)base + (size_t)a * N;
-                if (src_dtype == LBCG_DTYPE_F64)
-                    hipLaunchKernelGGL((raw_write_kernel<float, __half, double>), dim3(nb), dim3(256), 0, h->stream, d,
-                                       N, w, (const double*)in);
-                else
-                    hipLaunchKernelGGL((raw_write_kernel<float, __half, float>), dim3(nb), dim3(256), 0, h->stream, d,
-                                       N, w, (const float*)in);
+            switch (storage_kind(p, field)) {
+                case 0: raw_write_t<double, double>(p, base, field, a, N, in, src_dtype, h->stream); break;
+                case 1: raw_write_t<float, float>(p, base, field, a, N, in, src_dtype, h->stream); break;
+                default: raw_write_t<float, __half>(p, base, field, a, N, in, src_dtype, h->stream); break;
             }
             HIPCHK(hipGetLastError());
             if (!src_on_device) HIPCHK(hipStreamSynchronize(h->stream));  // staging is reused per plane
@@ -530,6 +642,91 @@ lbcg_status lbcg_growth_rates(lbcg_handle* h, double* G_out, double* R2_out, dou
         double Ga, R2a;
         fit([&](size_t j) { return avg[j]; }, Ga, R2a);
         if (G_avg_out) *G_avg_out = Ga;
+    });
+}
+
+int lbcg_variant_count(const lbcg_handle* h) { return h ? (int)h->variants.size() : -1; }
+
+int lbcg_variant_current(const lbcg_handle* h) { return h ? h->variant : -1; }
+
+lbcg_status lbcg_variant_name(const lbcg_handle* h, int idx, char* buf, size_t buflen) {
+    return guarded([&] {
+        if (!h || !buf || buflen == 0) throw Error(LBCG_EINVAL, "NULL handle or buffer");
+        if (idx < 0 || idx >= (int)h->variants.size()) throw Error(LBCG_EINVAL, "variant index out of range");
+        std::snprintf(buf, buflen, "%s", variant_name(h->variants[idx]).c_str());
+    });
+}
+
+namespace {
+void select_variant(lbcg_handle* h, int idx) {
+    if (idx < 0 || idx >= (int)h->variants.size()) throw Error(LBCG_EINVAL, "variant index out of range");
+    const Variant& v = h->variants[idx];
+    InstDev I = make_inst(&h->p, h->ws, h->L, v.tiling);
+    h->inst = I;
+    h->ops = v.ops;
+    h->variant = idx;
+}
+
+// Mean launch time of variant idx on the current state, which it leaves unchanged: the kernel
+// reads the current buffers and writes the other ones; phi_prev, updated in place, is saved to
+// the staging area and restored.
+double time_variant(lbcg_handle* h, int idx, int launches) {
+    const int keep = h->variant;
+    select_variant(h, idx);
+    const size_t pbytes = (size_t)h->inst.N * real_size(h->p.precision);
+    void* stage = h->ws + h->L.staging;
+    HIPCHK(hipMemcpyAsync(stage, h->inst.phi_prev, pbytes, hipMemcpyDeviceToDevice, h->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    h->ops->step(h->inst, h->par, h->stream);  // warm-up
+    HIPCHK(hipEventRecord(e0, h->stream));
+    for (int k = 0; k < launches; k++) h->ops->step(h->inst, h->par, h->stream);
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    HIPCHK(hipMemcpyAsync(h->inst.phi_prev, stage, pbytes, hipMemcpyDeviceToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    select_variant(h, keep);
+    return 1e3 * (double)ms / launches;
+}
+}  // namespace
+
+lbcg_status lbcg_variant_select(lbcg_handle* h, int idx) {
+    return guarded([&] {
+        if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
+        select_variant(h, idx);
+    });
+}
+
+lbcg_status lbcg_variant_time(lbcg_handle* h, int idx, int launches, double* us) {
+    return guarded([&] {
+        if (!h || !us) throw Error(LBCG_EINVAL, "NULL handle or output");
+        if (launches < 1) throw Error(LBCG_EINVAL, "launches must be >= 1");
+        *us = time_variant(h, idx, launches);
+    });
+}
+
+lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_us) {
+    return guarded([&] {
+        if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
+        if (launches < 1) throw Error(LBCG_EINVAL, "launches must be >= 1");
+        int bi = 0;
+        double bt = 1e300;
+        for (int i = 0; i < (int)h->variants.size(); i++) {
+            const double t = time_variant(h, i, launches);
+            if (t < bt) {
+                bt = t;
+                bi = i;
+            }
+        }
+        select_variant(h, bi);
+        if (best) *best = bi;
+        if (best_us) *best_us = bt;
     });
 }
 

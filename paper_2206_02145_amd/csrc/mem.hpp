@@ -1,0 +1,73 @@
+// mem.hpp -- population planes accessed through buffer descriptors.
+//
+// A population array is q planes of N values. Each plane gets its own buffer descriptor (base
+// address in SGPRs, extent = one plane), and a lane addresses a node with one 32-bit byte offset
+// shared by every plane: the address arithmetic of the up to 33 loads and stores of a node costs
+// one VGPR, and an offset outside the plane reads 0 / drops the store instead of touching other
+// memory.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+namespace lbcg {
+
+constexpr int BUF_RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
+
+template <typename T> struct BufOps;
+// AUX: cache-policy bits of the access (0 = default; 2 = non-temporal / streaming).
+template <> struct BufOps<float> {
+    template <int AUX = 0> __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+    }
+    template <int AUX = 0> __device__ static inline void st(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, AUX);
+    }
+};
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+template <> struct BufOps<double> {
+    template <int AUX = 0> __device__ static inline double ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+    }
+    template <int AUX = 0> __device__ static inline void st(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
+    }
+};
+template <> struct BufOps<__half> {
+    template <int AUX = 0> __device__ static inline __half ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+        return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX));
+    }
+    template <int AUX = 0> __device__ static inline void st(__amdgpu_buffer_rsrc_t r, unsigned off, __half v) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, AUX);
+    }
+};
+
+// q planes of N values of storage type T; loads convert to the compute type R. Stores use the
+// cache-policy bits AUX.
+template <typename T, int AUX = 0> struct Planes {
+    const char* base;
+    unsigned plane_bytes;  // N * sizeof(T), < 2^32
+
+    __device__ __forceinline__ Planes(const void* p, long long N)
+        : base(static_cast<const char*>(p)), plane_bytes((unsigned)(N * (long long)sizeof(T))) {}
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int a) const {
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(base + (size_t)a * plane_bytes), (short)0,
+                                                 (int)plane_bytes, BUF_RSRC_WORD3);
+    }
+    template <typename R> __device__ __forceinline__ R ld(int a, unsigned node) const {
+        if constexpr (std::is_same<T, __half>::value)
+            return (R)__half2float(BufOps<T>::template ld<0>(rsrc(a), node * 2u));
+        else
+            return (R)BufOps<T>::template ld<0>(rsrc(a), node * (unsigned)sizeof(T));
+    }
+    template <typename R> __device__ __forceinline__ void st(int a, unsigned node, R v) const {
+        if constexpr (std::is_same<T, __half>::value)
+            BufOps<T>::template st<AUX>(rsrc(a), node * 2u, __float2half_rn((float)v));
+        else
+            BufOps<T>::template st<AUX>(rsrc(a), node * (unsigned)sizeof(T), (T)v);
+    }
+};
+
+}  // namespace lbcg

@@ -26,6 +26,13 @@
 // and phi_prev is kept as psi_prev = phi_prev + 1. The collisions are written in these variables;
 // the a_s^2-weighted stream is unchanged by the shift because w_a = w_{opposite(a)}.
 //
+// Layout: a population with velocity component c_x = +-1 is stored shifted along its row, the
+// value of node x at memory column (x - c_x) mod nx (xmem below). The push stream then writes every
+// population of node x at memory column x of the destination row -- whole, aligned cache lines
+// per wavefront -- and the one-column shift moves to the loads, where a line split between two
+// wavefronts costs nothing extra. Rows, planes and lattice order are otherwise the plain SoA
+// [a][z][y][x]; the read/write entry points of the library convert to and from the plain layout.
+//
 // HBM traffic per node: every population read once and written once, plus phi_prev read and
 // written; halo re-reads of h are served by LDS and L2.
 #pragma once
@@ -34,6 +41,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lattice.hpp"
+#include "mem.hpp"
 
 namespace lbcg {
 
@@ -41,6 +49,7 @@ namespace lbcg {
 struct InstDev {
     int nx, ny, nz, xopen;
     int tiles_x, tiles_y, tiles_z, tile_begin;
+    int zc, pad_;                 // planes per workgroup of the z-marching kernel
     long long N;                  // nodes
     void* h[2];                   // ping-pong population arrays, planes [a][z][y][x]
     void* g[2];
@@ -62,6 +71,11 @@ template <> struct Store<float, __half> {
     __device__ static inline void st_(__half* p, long long i, float v) { p[i] = __float2half_rn(v); }
 };
 
+// Memory column of node column x for a population with x-velocity cx (see the layout note).
+__host__ __device__ __forceinline__ int xmem(int x, int cx, int nx) {
+    return cx == 0 ? x : (cx > 0 ? (x == 0 ? nx - 1 : x - 1) : (x == nx - 1 ? 0 : x + 1));
+}
+
 __device__ __forceinline__ int wrap_coord(int v, int n) {
     if (v < 0) v += n;
     if (v >= n) v -= n;
@@ -80,7 +94,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
     return xcd * per + (xcd < rem ? xcd : rem) + idx;
 }
 
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ>
+// PF: issue the own node's g, f and phi_prev loads before the barrier, so that their latency
+// overlaps the halo load of h. AUX: cache-policy bits of the population stores (0, or 2 = stream).
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0>
 __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, const int par) {
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
@@ -100,11 +116,31 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     const int tiz = trest / I.tiles_y;
     const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
 
-    const real* __restrict__ hin = static_cast<const real*>(I.h[par]);
-    real* __restrict__ hout = static_cast<real*>(I.h[par ^ 1]);
-    const real* __restrict__ gin = static_cast<const real*>(I.g[par]);
-    real* __restrict__ gout = static_cast<real*>(I.g[par ^ 1]);
-    real* __restrict__ pprev = static_cast<real*>(I.phi_prev);
+    const Planes<real, AUX> hin(I.h[par], N), hout(I.h[par ^ 1], N);
+    const Planes<real, AUX> gin(I.g[par], N), gout(I.g[par ^ 1], N);
+    const Planes<real> pprev(I.phi_prev, N);
+    const Planes<fst, AUX> fin(I.f[par], N), fout(I.f[par ^ 1], N);
+
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    const bool valid = x < nx && y < ny && z < nz;
+    const int xv = valid ? x : 0;
+    const unsigned rowO = valid ? (unsigned)((z * ny + y) * nx) : 0u;  // own row
+    const unsigned gi = rowO + (unsigned)xv;
+    real gv[S::Q];
+    real fv[V::Q];
+    real pp = 0;
+    auto load_own = [&]() {
+#pragma unroll
+        for (int a = 0; a < S::Q; a++) gv[a] = gin.template ld<real>(a, rowO + xmem(xv, S::c(a, 0), nx));
+        if constexpr (FLOW) {
+#pragma unroll
+            for (int a = 0; a < V::Q; a++)
+                fv[a] = fin.template ld<real>(a, rowO + xmem(xv, V::c(a, 0), nx));  // f - w
+        }
+        pp = pprev.template ld<real>(0, gi);
+    };
+    if constexpr (PF) load_own();
 
     // ---- phase 1: h and phi on the tile + halo ----
     for (int b = tid; b < NB; b += NT) {
@@ -117,11 +153,11 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         else gx = wrap_coord(gx, nx);
         const int gy = wrap_coord(y0 + by - 1, ny);
         const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
-        const long long gi = ((long long)gz * ny + gy) * nx + gx;
+        const unsigned rb = (unsigned)((gz * ny + gy) * nx);
         real phi = 0;
 #pragma unroll
         for (int a = 0; a < S::Q; a++) {
-            const real v = hin[a * N + gi];
+            const real v = hin.template ld<real>(a, rb + xmem(gx, S::c(a, 0), nx));
             s_h[a][b] = v;
             phi += v;
         }
@@ -130,11 +166,9 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     __syncthreads();
 
     // ---- phase 2: one node per thread ----
-    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-    if (x >= nx || y >= ny || z >= nz) return;
+    if (!valid) return;
+    if constexpr (!PF) load_own();
     const int bo = (DIM == 3 ? (lz + 1) * SZ : 0) + (ly + 1) * SY + (lx + 1);
-    const long long gi = ((long long)z * ny + y) * nx + x;
 
     // neighbour coordinates; -1 marks "through the inlet", nx marks "through the outlet"
     const bool xopen = I.xopen != 0;
@@ -145,10 +179,10 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     const int zp = (DIM == 3) ? ((z + 1 < nz) ? z + 1 : 0) : 0;
     const int zm = (DIM == 3) ? ((z > 0) ? z - 1 : nz - 1) : 0;
     auto dst_x = [&](int cx) { return cx > 0 ? xp : (cx < 0 ? xm : x); };
-    auto row = [&](int cy, int cz) -> long long {
+    auto row = [&](int cy, int cz) -> unsigned {
         const int yy = cy > 0 ? yp : (cy < 0 ? ym : y);
         const int zz = cz > 0 ? zp : (cz < 0 ? zm : z);
-        return ((long long)zz * ny + yy) * nx;
+        return (unsigned)((zz * ny + yy) * nx);
     };
     const bool at_outlet = xopen && (x == nx - 1);
 
@@ -191,13 +225,9 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     const real one_m_a2 = (real)1 - a2;
 
     // solute moment: Ut = U - U0
-    real gv[S::Q];
     real Ut = 0;
 #pragma unroll
-    for (int a = 0; a < S::Q; a++) {
-        gv[a] = gin[a * N + gi];
-        Ut += gv[a];
-    }
+    for (int a = 0; a < S::Q; a++) Ut += gv[a];
     const real U = Ut + (real)I.U0;
 
     // ---- phase field: Eq. (d) with the equilibrium of Eq. (e) ----
@@ -218,12 +248,12 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             if (xd >= 0 && xd < nx) {
                 const real hnb = s_h[a][bo + cx + cy * SY + (DIM == 3 ? cz * SZ : 0)];
                 const real v = (hs - one_m_a2 * hnb) * inv_a2;
-                hout[a * N + row(cy, cz) + xd] = v;
-                if (cx < 0 && at_outlet) hout[a * N + row(cy, cz) + x] = v;
+                hout.st(a, row(cy, cz) + x, v);  // memory column of node x + cx is x
+                if (cx < 0 && at_outlet) hout.st(a, row(cy, cz) + xmem(x, cx, nx), v);
             } else if (xd < 0) {  // inlet: bounce back into the opposite slot of this node
                 const int b = S::opp(a);
                 const real v = (hs - one_m_a2 * s_h[b][bo]) * inv_a2;
-                hout[b * N + gi] = v;
+                hout.st(b, rowO + xmem(x, S::c(b, 0), nx), v);
             }
         }
     }
@@ -231,13 +261,9 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     // ---- flow: BGK + Guo forcing of the drag, u* in the equilibrium ----
     real usx = 0, usy = 0, usz = 0;
     if constexpr (FLOW) {
-        const fst* __restrict__ fin = static_cast<const fst*>(I.f[par]);
-        fst* __restrict__ fout = static_cast<fst*>(I.f[par ^ 1]);
-        real fv[V::Q];
         real drho = 0, mx = 0, my = 0, mz = 0;
 #pragma unroll
         for (int a = 0; a < V::Q; a++) {
-            fv[a] = Store<real, fst>::ld(fin, a * N + gi);  // f - w
             drho += fv[a];
             if (V::c(a, 0)) mx += (real)V::c(a, 0) * fv[a];
             if (V::c(a, 1)) my += (real)V::c(a, 1) * fv[a];
@@ -269,11 +295,11 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             const real fs = fv[a] - (fv[a] - feq) * inv_tau_f + Sa;
             const int xd = dst_x(cx);
             if (xd >= 0 && xd < nx) {
-                Store<real, fst>::st_(fout, a * N + row(cy, cz) + xd, fs);
-                if (cx < 0 && at_outlet) Store<real, fst>::st_(fout, a * N + row(cy, cz) + x, fs);
+                fout.st(a, row(cy, cz) + x, fs);
+                if (cx < 0 && at_outlet) fout.st(a, row(cy, cz) + xmem(x, cx, nx), fs);
             } else if (xd < 0) {  // velocity bounce-back, wall density 1
                 const int b = V::opp(a);
-                Store<real, fst>::st_(fout, b * N + gi, fs - (real)6 * wa * (real)cx * uinx);
+                fout.st(b, rowO + xmem(x, V::c(b, 0), nx), fs - (real)6 * wa * (real)cx * uinx);
             }
         }
     }
@@ -283,7 +309,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         real q = two_m_psi;  // 1 - phi, clamped to [0, 2]
         q = q < (real)0 ? (real)0 : (q > (real)2 ? (real)2 : q);
         const real inv_tau_U = (real)1 / ((real)(I.D * S::inv_cs2) * q + (real)0.5);
-        const real dphi = psi - pprev[gi];
+        const real dphi = psi - pp;
         const real Uin2 = (real)2 * (real)(I.U_in - I.U0);
 #pragma unroll
         for (int a = 0; a < S::Q; a++) {
@@ -294,19 +320,19 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             const real gs = gv[a] - (gv[a] - geq) * inv_tau_U - wa * dphi;
             const int xd = dst_x(cx);
             if (xd >= 0 && xd < nx) {
-                gout[a * N + row(cy, cz) + xd] = gs;
-                if (cx < 0 && at_outlet) gout[a * N + row(cy, cz) + x] = gs;
+                gout.st(a, row(cy, cz) + x, gs);
+                if (cx < 0 && at_outlet) gout.st(a, row(cy, cz) + xmem(x, cx, nx), gs);
             } else if (xd < 0) {  // anti-bounce-back, U = U_in on the inlet wall
-                gout[S::opp(a) * N + gi] = -gs + wa * Uin2;
+                gout.st(S::opp(a), rowO + xmem(x, S::c(S::opp(a), 0), nx), -gs + wa * Uin2);
             }
         }
     }
-    pprev[gi] = psi;
+    pprev.st(0, gi, psi);
 }
 
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ>
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX>
 __global__ __launch_bounds__(TX* TY* TZ) void step_single(InstDev I, int par) {
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ>(I, xcd_tile(blockIdx.x, gridDim.x), par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX>(I, xcd_tile(blockIdx.x, gridDim.x), par);
 }
 
 // Batched launch: the tiles of all instances form one list; each workgroup finds its instance

@@ -67,10 +67,18 @@ def lib():
         L.lbcg_measure.argtypes = [vp, i32, dp, dp, dp]
         L.lbcg_growth_rates.argtypes = [vp, dp, dp, dp]
         L.lbcg_destroy.argtypes = [vp]
+        L.lbcg_variant_count.argtypes = [vp]
+        L.lbcg_variant_current.argtypes = [vp]
+        L.lbcg_variant_name.argtypes = [vp, i32, ctypes.c_char_p, sz]
+        L.lbcg_variant_select.argtypes = [vp, i32]
+        L.lbcg_variant_time.argtypes = [vp, i32, i32, dp]
+        L.lbcg_autotune.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int), dp]
         L.lbcg_last_error.argtypes = []
         L.lbcg_last_error.restype = ctypes.c_char_p
         for name in ("lbcg_create", "lbcg_step", "lbcg_read_field", "lbcg_write_field",
-                     "lbcg_measure", "lbcg_growth_rates", "lbcg_destroy"):
+                     "lbcg_measure", "lbcg_growth_rates", "lbcg_destroy", "lbcg_variant_name",
+                     "lbcg_variant_select", "lbcg_variant_time", "lbcg_autotune", "lbcg_variant_count",
+                     "lbcg_variant_current"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -185,6 +193,34 @@ class Solver:
         Ga = ctypes.c_double()
         check(lib().lbcg_growth_rates(self.handle, _dptr(G), _dptr(R2), ctypes.byref(Ga)), "lbcg_growth_rates")
         return G, R2, Ga.value
+
+    # ---- kernel variants / autotuning ----
+    def variants(self):
+        n = lib().lbcg_variant_count(self.handle)
+        out = []
+        buf = ctypes.create_string_buffer(128)
+        for i in range(n):
+            check(lib().lbcg_variant_name(self.handle, i, buf, 128), "lbcg_variant_name")
+            out.append(buf.value.decode())
+        return out
+
+    @property
+    def variant(self) -> int:
+        return int(lib().lbcg_variant_current(self.handle))
+
+    def select_variant(self, idx: int):
+        check(lib().lbcg_variant_select(self.handle, int(idx)), "lbcg_variant_select")
+
+    def time_variant(self, idx: int, launches: int = 20) -> float:
+        us = ctypes.c_double()
+        check(lib().lbcg_variant_time(self.handle, int(idx), int(launches), ctypes.byref(us)), "lbcg_variant_time")
+        return us.value
+
+    def autotune(self, launches: int = 20):
+        best = ctypes.c_int()
+        us = ctypes.c_double()
+        check(lib().lbcg_autotune(self.handle, int(launches), ctypes.byref(best), ctypes.byref(us)), "lbcg_autotune")
+        return best.value, us.value
 
     def close(self):
         if getattr(self, "handle", None):

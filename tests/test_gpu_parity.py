@@ -234,3 +234,32 @@ def test_nonfinite_is_reported(lb):
         s.step(1)
     assert e.value.status == "ENONFINITE"
     s.close()
+
+
+# ---- kernel variants ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg,prec", [("c3small", "fp32"), ("c3small", "fp64"), ("c2small", "fp32"),
+                                      ("c1small", "fp32"), ("c4inst", "fp16shift")])
+def test_every_variant_computes_the_same_step(lb, cfg, prec):
+    """All tilings of the step kernel give the same state (the autotuner may pick any of them)."""
+    p = {"c3small": W.scaled(W.config3(), 70, 20, 18, seed_R=6.0),
+         "c2small": W.scaled(W.config2(), 40, 24, 20, seed_R=6.0),
+         "c1small": W.scaled(W.config1(), 100, 36, 1, seed_R=8.0),
+         "c4inst": W.sweep_instance(96, 0.3, 8.0, 0.02)}[cfg]
+    ref = None
+    s0 = lb.Solver(p, prec)
+    names = s0.variants()
+    s0.close()
+    print(f"[parity] variants {cfg} {prec}: {names}", flush=True)
+    for k, name in enumerate(names):
+        s = lb.Solver(p, prec)
+        s.select_variant(k)
+        s.step(25)
+        state = [s.read(f) for f in ("raw_h", "raw_g", "phi_prev") + (("raw_f",) if p["flow"] else ())]
+        s.close()
+        if ref is None:
+            ref = state
+            continue
+        for a, b in zip(state, ref):
+            err = np.abs(a - b).max() / np.abs(b).max()
+            assert err < (1e-12 if prec == "fp64" else 1e-5), (name, err)
