@@ -164,6 +164,40 @@ lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_
 /* Release the host handle (the workspace stays the caller's). NULL is accepted. */
 lbcg_status lbcg_destroy(lbcg_handle* h);
 
+/* ---- Batches: many independent grids of one kind advanced by one launch per step ----
+ * The parametric studies of the paper (Section 4.1.3 supersaturation, 4.1.4 seed size, 4.2
+ * inflow velocity) run many small grids; a batch steps all of them with one kernel launch per step
+ * (a list of the tiles of every instance), optionally replayed from a captured HIP graph. Every
+ * instance computes exactly what a single solver with the same parameters computes. All instances
+ * must share dim, flow and precision; sizes and physical parameters may differ. */
+
+/* Device workspace bytes for n instances (0 if any parameter set is invalid). */
+size_t lbcg_batch_workspace_bytes(int n, const lbcg_params* p /* n */);
+
+/* As lbcg_create, for n instances in one caller-owned workspace; synchronises. */
+lbcg_status lbcg_batch_create(int n, const lbcg_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+                              lbcg_batch** out);
+
+/* Advance every instance nsteps steps. If measure_every > 0 and ndirs > 0, after every
+ * measure_every steps the crystal extent of every instance along each unit direction (as in
+ * lbcg_measure) is appended to L_hist, laid out [sample][instance][direction] with
+ * floor(nsteps / measure_every) samples. use_graph != 0 replays each measure_every-step chunk from
+ * a captured HIP graph (needs a non-null stream). Synchronises. */
+lbcg_status lbcg_batch_run(lbcg_batch* b, int64_t nsteps, int64_t measure_every, int ndirs, const double* dirs,
+                           double* L_hist, int use_graph);
+
+/* Crystal extent of every instance now: L_out[instance * ndirs + k]. Synchronises. */
+lbcg_status lbcg_batch_measure(lbcg_batch* b, int ndirs, const double* dirs, double* L_out);
+
+/* lbcg_read_field for instance `inst`. */
+lbcg_status lbcg_batch_read_field(lbcg_batch* b, int inst, int field, void* dst, size_t dst_bytes,
+                                  int dst_on_device, int dst_dtype);
+
+int64_t lbcg_batch_step_count(const lbcg_batch* b);  /* -1 for NULL */
+
+/* Release the host state and captured graphs (the workspace stays the caller's). NULL accepted. */
+lbcg_status lbcg_batch_destroy(lbcg_batch* b);
+
 /* Message of the calling thread's last error ("" if none). */
 const char* lbcg_last_error(void);
 

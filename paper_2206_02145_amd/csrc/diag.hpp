@@ -239,25 +239,25 @@ __device__ inline double phi_interp(const InstDev& I, const real* h, const doubl
     return v;
 }
 
-// One 64-lane workgroup per direction. Lane j of a round tests sample j+1: the first sample that
-// leaves the domain or has phi <= 0 ends the ray (all earlier samples have phi > 0).
+// Crystal extent along one direction dv from centre c, computed by one 64-lane wavefront. Lane j
+// of a round tests sample j+1: the first sample that leaves the domain or has phi <= 0 ends the
+// ray (all earlier samples have phi > 0). Lane 0 writes the result.
 template <int DIM, typename real>
-__global__ __launch_bounds__(64) void raymarch_kernel(InstDev I, int par, const double* dirs,
-                                                      double cx, double cy, double cz, double* L_out) {
-    const int k = blockIdx.x;
+__device__ inline void raymarch_one(const InstDev& I, int par, const double* dv_in, const double* c_in,
+                                    double* L_out) {
     const int lane = threadIdx.x;
     const real* h = static_cast<const real*>(I.h[par]);
     const double ds = 0.25;
-    const double c[3] = {cx, cy, DIM == 3 ? cz : 0.0};
-    const double dv[3] = {dirs[3 * k], dirs[3 * k + 1], DIM == 3 ? dirs[3 * k + 2] : 0.0};
+    const double c[3] = {c_in[0], c_in[1], DIM == 3 ? c_in[2] : 0.0};
+    const double dv[3] = {dv_in[0], dv_in[1], DIM == 3 ? dv_in[2] : 0.0};
     const double n[3] = {(double)I.nx, (double)I.ny, (double)I.nz};
     const double phic = phi_interp<DIM, real>(I, h, c);
     if (!(phic > 0.0)) {
-        if (lane == 0) L_out[k] = 0.0;
+        if (lane == 0) *L_out = 0.0;
         return;
     }
     for (long long base = 0;; base += 64) {
-        const long long j = base + lane;  // this lane tests sample j + 1 against sample j
+        const long long j = base + lane;
         const double s1 = (double)(j + 1) * ds;
         const double pt[3] = {c[0] + s1 * dv[0], c[1] + s1 * dv[1], c[2] + s1 * dv[2]};
         bool out = false;
@@ -275,16 +275,35 @@ __global__ __launch_bounds__(64) void raymarch_kernel(InstDev I, int par, const 
                 if (out) {
                     L = sj;
                 } else {
-                    const double s0 = sj;
-                    const double p0[3] = {c[0] + s0 * dv[0], c[1] + s0 * dv[1], c[2] + s0 * dv[2]};
+                    const double p0[3] = {c[0] + sj * dv[0], c[1] + sj * dv[1], c[2] + sj * dv[2]};
                     const double prev = (j == 0) ? phic : phi_interp<DIM, real>(I, h, p0);
                     L = sj + ds * prev / (prev - cur);
                 }
-                L_out[k] = L;
+                *L_out = L;
             }
             return;
         }
     }
+}
+
+// One workgroup per direction.
+template <int DIM, typename real>
+__global__ __launch_bounds__(64) void raymarch_kernel(InstDev I, int par, const double* dirs,
+                                                      double cx, double cy, double cz, double* L_out) {
+    const int k = blockIdx.x;
+    const double c[3] = {cx, cy, cz};
+    raymarch_one<DIM, real>(I, par, dirs + 3 * k, c, L_out + k);
+}
+
+// Batched: workgroup (k, i) marches direction k of instance i from that instance's seed centre;
+// out[i * ndirs + k].
+template <int DIM, typename real>
+__global__ __launch_bounds__(64) void raymarch_batch_kernel(const InstDev* __restrict__ insts, int par,
+                                                            const double* dirs, int ndirs,
+                                                            const double* centers, double* out) {
+    const int k = blockIdx.x, i = blockIdx.y;
+    const InstDev I = insts[i];
+    raymarch_one<DIM, real>(I, par, dirs + 3 * k, centers + 3 * i, out + (size_t)i * ndirs + k);
 }
 
 }  // namespace lbcg

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -268,11 +269,12 @@ template <int DIM, bool FLOW, typename real, typename fst>
 void block_variants(std::vector<Variant>& v) {
     auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
     if constexpr (DIM == 2) {
-        static const Ops a = BlockOps<2, FLOW, real, fst, 64, 4, 1, true>::ops();
-        static const Ops b = BlockOps<2, FLOW, real, fst, 64, 4, 1>::ops();
-        static const Ops c = BlockOps<2, FLOW, real, fst, 64, 2, 1, true>::ops();
-        static const Ops d = BlockOps<2, FLOW, real, fst, 64, 8, 1, true>::ops();
-        static const Ops e = BlockOps<2, FLOW, real, fst, 128, 2, 1, true>::ops();
+        // first = default, also the tiling of the batched launch
+        static const Ops a = BlockOps<2, FLOW, real, fst, 64, 4, 1, false, sizeof(real) == 8 ? 0 : 2>::ops();
+        static const Ops b = BlockOps<2, FLOW, real, fst, 64, 4, 1, true>::ops();
+        static const Ops c = BlockOps<2, FLOW, real, fst, 64, 2, 1, true, 2>::ops();
+        static const Ops d = BlockOps<2, FLOW, real, fst, 64, 8, 1, false, 2>::ops();
+        static const Ops e = BlockOps<2, FLOW, real, fst, 128, 2, 1, false, 2>::ops();
         for (const Ops* o : {&a, &b, &c, &d, &e}) add(*o);
     } else if constexpr (sizeof(real) == 8) {
         static const Ops a = BlockOps<3, FLOW, real, fst, 16, 4, 4>::ops();
@@ -384,7 +386,119 @@ int storage_kind(const lbcg_params& p, int field) {  // 0 double, 1 float, 2 hal
 }
 
 
+// ---- batched launches (many independent grids of one kind) ----
+struct BatchKit {
+    Tiling tiling;
+    void (*step)(const InstDev* d, int n, int tiles, int par, hipStream_t);
+    void (*ray)(const InstDev* d, int n, int par, const double* dirs, int ndirs, const double* centers,
+                double* out, hipStream_t);
+};
+
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX>
+struct BatchImpl {
+    static void step(const InstDev* d, int n, int tiles, int par, hipStream_t s) {
+        hipLaunchKernelGGL((step_batch<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX>), dim3(tiles), dim3(TX * TY * TZ),
+                           0, s, d, n, par);
+    }
+    static void ray(const InstDev* d, int n, int par, const double* dirs, int ndirs, const double* centers,
+                    double* out, hipStream_t s) {
+        hipLaunchKernelGGL((raymarch_batch_kernel<DIM, real>), dim3(ndirs, n), dim3(64), 0, s, d, par, dirs, ndirs,
+                           centers, out);
+    }
+    static BatchKit kit() { return BatchKit{Tiling{false, TX, TY, TZ, PF, AUX}, step, ray}; }
+};
+
+const BatchKit& batch_kit_for(int dim, int flow, int prec) {
+    static const BatchKit k2[2][3] = {
+        {BatchImpl<2, false, double, double, 64, 4, 1, false, 0>::kit(), BatchImpl<2, false, float, float, 64, 4, 1, false, 2>::kit(),
+         BatchImpl<2, false, float, float, 64, 4, 1, false, 2>::kit()},
+        {BatchImpl<2, true, double, double, 64, 4, 1, false, 0>::kit(), BatchImpl<2, true, float, float, 64, 4, 1, false, 2>::kit(),
+         BatchImpl<2, true, float, __half, 64, 4, 1, false, 2>::kit()}};
+    static const BatchKit k3[2][3] = {
+        {BatchImpl<3, false, double, double, 16, 4, 4, false, 0>::kit(), BatchImpl<3, false, float, float, 64, 2, 4, false, 2>::kit(),
+         BatchImpl<3, false, float, float, 64, 2, 4, false, 2>::kit()},
+        {BatchImpl<3, true, double, double, 16, 4, 4, false, 0>::kit(), BatchImpl<3, true, float, float, 64, 2, 4, false, 2>::kit(),
+         BatchImpl<3, true, float, __half, 64, 2, 4, false, 2>::kit()}};
+    return dim == 2 ? k2[flow][prec] : k3[flow][prec];
+}
+
+// Per-instance population buffers inside a batch workspace (the single-grid layout without its
+// staging and diagnostics areas).
+Layout instance_layout(const lbcg_params* p, size_t& off) {
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    const size_t rs = real_size(p->precision), fs = fstore_size(p->precision);
+    Layout L{};
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    for (int k = 0; k < 2; k++) L.h[k] = take(qs_of(p->dim) * N * rs);
+    for (int k = 0; k < 2; k++) L.g[k] = take(qs_of(p->dim) * N * rs);
+    for (int k = 0; k < 2; k++) L.f[k] = p->flow ? take(qf_of(p->dim) * N * fs) : 0;
+    L.phi_prev = take(N * rs);
+    return L;
+}
+
+struct BatchLayout {
+    std::vector<Layout> inst;
+    size_t table, centers, dirs, Lout, staging, total;
+};
+
+BatchLayout batch_layout(int n, const lbcg_params* p) {
+    BatchLayout B;
+    size_t off = 0, maxN = 0;
+    for (int i = 0; i < n; i++) {
+        B.inst.push_back(instance_layout(&p[i], off));
+        maxN = std::max(maxN, (size_t)p[i].nx * p[i].ny * p[i].nz);
+    }
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    B.table = take(sizeof(InstDev) * n);
+    B.centers = take(sizeof(double) * 3 * n);
+    B.dirs = take(sizeof(double) * 3 * MAX_DIRS);
+    B.Lout = take(sizeof(double) * MAX_DIRS * n);
+    B.staging = take(maxN * 8);
+    B.total = off;
+    return B;
+}
+
+void validate_batch(int n, const lbcg_params* p) {
+    if (n < 1 || n > 65535) throw Error(LBCG_EINVAL, "batch size must be in [1, 65535]");
+    if (!p) throw Error(LBCG_EINVAL, "params is NULL");
+    long long tiles = 0;
+    for (int i = 0; i < n; i++) {
+        validate(&p[i]);
+        if (p[i].dim != p[0].dim || p[i].flow != p[0].flow || p[i].precision != p[0].precision)
+            throw Error(LBCG_EINVAL, "all instances of a batch need the same dim, flow and precision");
+        tiles += (long long)p[i].nx * p[i].ny * p[i].nz;
+    }
+    if (tiles > (1LL << 31)) throw Error(LBCG_EINVAL, "batch too large");
+}
+
 }  // namespace
+
+struct lbcg_batch {
+    int n;
+    std::vector<lbcg_params> p;
+    std::vector<InstDev> inst;
+    BatchLayout L;
+    char* ws;
+    hipStream_t stream;
+    const BatchKit* kit;
+    const Ops* common;  // init / field kernels of the instance kind
+    int total_tiles;
+    int par;
+    int64_t nstep;
+    struct Graph {
+        hipGraphExec_t exec;
+        int par, steps, ndirs;
+    };
+    std::vector<Graph> graphs;
+};
 
 struct lbcg_handle {
     lbcg_params p;
@@ -472,80 +586,97 @@ lbcg_status lbcg_step(lbcg_handle* h, int64_t nsteps) {
 
 int64_t lbcg_step_count(const lbcg_handle* h) { return h ? h->nstep : -1; }
 
+}  // extern "C"
+
+namespace {
+
+int planes_of(const lbcg_params& p, int field) {
+    return field == LBCG_FIELD_RAW_H || field == LBCG_FIELD_RAW_G ? qs_of(p.dim)
+           : field == LBCG_FIELD_RAW_F                           ? qf_of(p.dim)
+                                                                 : 1;
+}
+
+void read_field_impl(const lbcg_params& p, const InstDev& I, int par, void* stage, const Ops* ops,
+                     hipStream_t stream, int field, void* dst, size_t dst_bytes, int dst_on_device, int dst_dtype) {
+    if (!dst) throw Error(LBCG_EINVAL, "NULL destination");
+    if (dst_dtype != LBCG_DTYPE_F64 && dst_dtype != LBCG_DTYPE_F32) throw Error(LBCG_EINVAL, "bad dtype");
+    if (field < LBCG_FIELD_PHI || field > LBCG_FIELD_RAW_F) throw Error(LBCG_EINVAL, "bad field id");
+    if (field == LBCG_FIELD_RAW_F && !p.flow) throw Error(LBCG_EINVAL, "no flow lattice");
+    const long long N = I.N;
+    const size_t es = dst_dtype == LBCG_DTYPE_F64 ? 8 : 4;
+    const int planes = planes_of(p, field);
+    if (dst_bytes < (size_t)planes * N * es) throw Error(LBCG_ENOMEM, "destination too small");
+    for (int a = 0; a < planes; a++) {
+        void* tgt = dst_on_device ? (char*)dst + (size_t)a * N * es : stage;
+        if (field < LBCG_FIELD_RAW_H) {
+            ops->field(I, par, field, tgt, dst_dtype, stream);
+        } else {
+            const void* base = field == LBCG_FIELD_RAW_H ? I.h[par] : field == LBCG_FIELD_RAW_G ? I.g[par] : I.f[par];
+            switch (storage_kind(p, field)) {
+                case 0: raw_read_t<double, double>(p, base, field, a, N, tgt, dst_dtype, stream); break;
+                case 1: raw_read_t<float, float>(p, base, field, a, N, tgt, dst_dtype, stream); break;
+                default: raw_read_t<float, __half>(p, base, field, a, N, tgt, dst_dtype, stream); break;
+            }
+        }
+        HIPCHK(hipGetLastError());
+        if (!dst_on_device)
+            HIPCHK(hipMemcpyAsync((char*)dst + (size_t)a * N * es, stage, N * es, hipMemcpyDeviceToHost, stream));
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+}
+
+void write_field_impl(const lbcg_params& p, const InstDev& I, int par, void* stage, hipStream_t stream, int field,
+                      const void* src, size_t src_bytes, int src_on_device, int src_dtype) {
+    if (!src) throw Error(LBCG_EINVAL, "NULL source");
+    if (src_dtype != LBCG_DTYPE_F64 && src_dtype != LBCG_DTYPE_F32) throw Error(LBCG_EINVAL, "bad dtype");
+    if (field != LBCG_FIELD_PHI_PREV && field != LBCG_FIELD_RAW_H && field != LBCG_FIELD_RAW_G &&
+        field != LBCG_FIELD_RAW_F)
+        throw Error(LBCG_EINVAL, "only RAW_* and PHI_PREV can be written");
+    if (field == LBCG_FIELD_RAW_F && !p.flow) throw Error(LBCG_EINVAL, "no flow lattice");
+    const long long N = I.N;
+    const size_t es = src_dtype == LBCG_DTYPE_F64 ? 8 : 4;
+    const int planes = planes_of(p, field);
+    if (src_bytes < (size_t)planes * N * es) throw Error(LBCG_ENOMEM, "source too small");
+    for (int a = 0; a < planes; a++) {
+        const void* in = (const char*)src + (size_t)a * N * es;
+        if (!src_on_device) {
+            HIPCHK(hipMemcpyAsync(stage, in, N * es, hipMemcpyHostToDevice, stream));
+            in = stage;
+        }
+        void* base = field == LBCG_FIELD_RAW_H   ? I.h[par]
+                     : field == LBCG_FIELD_RAW_G ? I.g[par]
+                     : field == LBCG_FIELD_RAW_F ? I.f[par]
+                                                 : I.phi_prev;
+        switch (storage_kind(p, field)) {
+            case 0: raw_write_t<double, double>(p, base, field, a, N, in, src_dtype, stream); break;
+            case 1: raw_write_t<float, float>(p, base, field, a, N, in, src_dtype, stream); break;
+            default: raw_write_t<float, __half>(p, base, field, a, N, in, src_dtype, stream); break;
+        }
+        HIPCHK(hipGetLastError());
+        if (!src_on_device) HIPCHK(hipStreamSynchronize(stream));  // the staging area is reused per plane
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+}
+
+}  // namespace
+
+extern "C" {
+
 lbcg_status lbcg_read_field(lbcg_handle* h, int field, void* dst, size_t dst_bytes, int dst_on_device,
                             int dst_dtype) {
     return guarded([&] {
-        if (!h || !dst) throw Error(LBCG_EINVAL, "NULL handle or destination");
-        if (dst_dtype != LBCG_DTYPE_F64 && dst_dtype != LBCG_DTYPE_F32) throw Error(LBCG_EINVAL, "bad dtype");
-        if (field < LBCG_FIELD_PHI || field > LBCG_FIELD_RAW_F) throw Error(LBCG_EINVAL, "bad field id");
-        if (field == LBCG_FIELD_RAW_F && !h->p.flow) throw Error(LBCG_EINVAL, "no flow lattice");
-        const lbcg_params& p = h->p;
-        const long long N = h->inst.N;
-        const size_t es = dst_dtype == LBCG_DTYPE_F64 ? 8 : 4;
-        const int planes = field == LBCG_FIELD_RAW_H || field == LBCG_FIELD_RAW_G ? qs_of(p.dim)
-                           : field == LBCG_FIELD_RAW_F                           ? qf_of(p.dim)
-                                                                                 : 1;
-        if (dst_bytes < (size_t)planes * N * es) throw Error(LBCG_ENOMEM, "destination too small");
-        void* stage = h->ws + h->L.staging;
-        for (int a = 0; a < planes; a++) {
-            void* tgt = dst_on_device ? (char*)dst + (size_t)a * N * es : stage;
-            if (field < LBCG_FIELD_RAW_H) {
-                h->ops->field(h->inst, h->par, field, tgt, dst_dtype, h->stream);
-            } else {
-                const void* base = field == LBCG_FIELD_RAW_H ? h->inst.h[h->par]
-                                   : field == LBCG_FIELD_RAW_G ? h->inst.g[h->par]
-                                                               : h->inst.f[h->par];
-                switch (storage_kind(p, field)) {
-                    case 0: raw_read_t<double, double>(p, base, field, a, N, tgt, dst_dtype, h->stream); break;
-                    case 1: raw_read_t<float, float>(p, base, field, a, N, tgt, dst_dtype, h->stream); break;
-                    default: raw_read_t<float, __half>(p, base, field, a, N, tgt, dst_dtype, h->stream); break;
-                }
-            }
-            HIPCHK(hipGetLastError());
-            if (!dst_on_device)
-                HIPCHK(hipMemcpyAsync((char*)dst + (size_t)a * N * es, stage, N * es, hipMemcpyDeviceToHost,
-                                      h->stream));
-        }
-        HIPCHK(hipStreamSynchronize(h->stream));
+        if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
+        read_field_impl(h->p, h->inst, h->par, h->ws + h->L.staging, h->ops, h->stream, field, dst, dst_bytes,
+                        dst_on_device, dst_dtype);
     });
 }
 
 lbcg_status lbcg_write_field(lbcg_handle* h, int field, const void* src, size_t src_bytes, int src_on_device,
                              int src_dtype) {
     return guarded([&] {
-        if (!h || !src) throw Error(LBCG_EINVAL, "NULL handle or source");
-        if (src_dtype != LBCG_DTYPE_F64 && src_dtype != LBCG_DTYPE_F32) throw Error(LBCG_EINVAL, "bad dtype");
-        if (field != LBCG_FIELD_PHI_PREV && field != LBCG_FIELD_RAW_H && field != LBCG_FIELD_RAW_G &&
-            field != LBCG_FIELD_RAW_F)
-            throw Error(LBCG_EINVAL, "only RAW_* and PHI_PREV can be written");
-        if (field == LBCG_FIELD_RAW_F && !h->p.flow) throw Error(LBCG_EINVAL, "no flow lattice");
-        const lbcg_params& p = h->p;
-        const long long N = h->inst.N;
-        const size_t es = src_dtype == LBCG_DTYPE_F64 ? 8 : 4;
-        const int planes = field == LBCG_FIELD_RAW_H || field == LBCG_FIELD_RAW_G ? qs_of(p.dim)
-                           : field == LBCG_FIELD_RAW_F                           ? qf_of(p.dim)
-                                                                                 : 1;
-        if (src_bytes < (size_t)planes * N * es) throw Error(LBCG_ENOMEM, "source too small");
-        void* stage = h->ws + h->L.staging;
-        for (int a = 0; a < planes; a++) {
-            const void* in = (const char*)src + (size_t)a * N * es;
-            if (!src_on_device) {
-                HIPCHK(hipMemcpyAsync(stage, in, N * es, hipMemcpyHostToDevice, h->stream));
-                in = stage;
-            }
-            void* base = field == LBCG_FIELD_RAW_H   ? h->inst.h[h->par]
-                         : field == LBCG_FIELD_RAW_G ? h->inst.g[h->par]
-                         : field == LBCG_FIELD_RAW_F ? h->inst.f[h->par]
-                                                     : h->inst.phi_prev;
-            switch (storage_kind(p, field)) {
-                case 0: raw_write_t<double, double>(p, base, field, a, N, in, src_dtype, h->stream); break;
-                case 1: raw_write_t<float, float>(p, base, field, a, N, in, src_dtype, h->stream); break;
-                default: raw_write_t<float, __half>(p, base, field, a, N, in, src_dtype, h->stream); break;
-            }
-            HIPCHK(hipGetLastError());
-            if (!src_on_device) HIPCHK(hipStreamSynchronize(h->stream));  // staging is reused per plane
-        }
-        HIPCHK(hipStreamSynchronize(h->stream));
+        if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
+        write_field_impl(h->p, h->inst, h->par, h->ws + h->L.staging, h->stream, field, src, src_bytes,
+                         src_on_device, src_dtype);
     });
 }
 
@@ -732,6 +863,174 @@ lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_
 
 lbcg_status lbcg_destroy(lbcg_handle* h) {
     delete h;
+    return LBCG_OK;
+}
+
+// ---- batches ----
+
+size_t lbcg_batch_workspace_bytes(int n, const lbcg_params* p) {
+    try {
+        validate_batch(n, p);
+        return batch_layout(n, p).total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+lbcg_status lbcg_batch_create(int n, const lbcg_params* p, void* dev_workspace, size_t bytes, void* hip_stream,
+                              lbcg_batch** out) {
+    if (out) *out = nullptr;
+    lbcg_batch* b = nullptr;
+    lbcg_status st = guarded([&] {
+        if (!out) throw Error(LBCG_EINVAL, "out is NULL");
+        validate_batch(n, p);
+        BatchLayout L = batch_layout(n, p);
+        if (!dev_workspace) throw Error(LBCG_EINVAL, "workspace is NULL");
+        if (((uintptr_t)dev_workspace & 255) != 0) throw Error(LBCG_EINVAL, "workspace must be 256-byte aligned");
+        if (bytes < L.total) throw Error(LBCG_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+        b = new lbcg_batch();
+        b->n = n;
+        b->p.assign(p, p + n);
+        b->L = L;
+        b->ws = (char*)dev_workspace;
+        b->stream = (hipStream_t)hip_stream;
+        b->kit = &batch_kit_for(p[0].dim, p[0].flow, p[0].precision);
+        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx)[0].ops;
+        b->par = 0;
+        b->nstep = 0;
+        int tiles = 0;
+        std::vector<double> centers(3 * n);
+        for (int i = 0; i < n; i++) {
+            InstDev I = make_inst(&p[i], b->ws, L.inst[i], b->kit->tiling);
+            I.tile_begin = tiles;
+            tiles += I.tiles_x * I.tiles_y * I.tiles_z;
+            b->inst.push_back(I);
+            for (int d = 0; d < 3; d++) centers[3 * i + d] = p[i].seed_center[d];
+        }
+        b->total_tiles = tiles;
+        HIPCHK(hipMemsetAsync(b->ws, 0, L.table, b->stream));
+        HIPCHK(hipMemcpyAsync(b->ws + L.table, b->inst.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(b->ws + L.centers, centers.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice,
+                              b->stream));
+        for (int i = 0; i < n; i++) {
+            SeedArgs a{p[i].seed_center[0], p[i].seed_center[1], p[i].seed_center[2], p[i].seed_radius, p[i].W0,
+                       p[i].U0, p[i].flow ? p[i].u_inlet : 0.0};
+            b->common->init(b->inst[i], 0, a, b->stream);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(b->stream));
+    });
+    if (st != LBCG_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return LBCG_OK;
+}
+
+namespace {
+void check_dirs(int dim, int ndirs, const double* dirs) {
+    if (ndirs < 0 || ndirs > MAX_DIRS) throw Error(LBCG_EINVAL, "ndirs must be in [0, 256]");
+    if (ndirs > 0 && !dirs) throw Error(LBCG_EINVAL, "dirs is NULL");
+    for (int k = 0; k < ndirs; k++) {
+        const double* d = dirs + 3 * k;
+        const double n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (!(std::fabs(n2 - 1.0) < 1e-6)) throw Error(LBCG_EINVAL, "directions must be unit vectors");
+        if (dim == 2 && d[2] != 0.0) throw Error(LBCG_EINVAL, "2-D directions need z = 0");
+    }
+}
+
+// Enqueue `steps` batched steps from parity par (and the ray-march into the L slot if ndirs > 0).
+void batch_chunk(lbcg_batch* b, int par, int steps, int ndirs) {
+    const InstDev* d = (const InstDev*)(b->ws + b->L.table);
+    for (int k = 0; k < steps; k++) {
+        b->kit->step(d, b->n, b->total_tiles, par, b->stream);
+        par ^= 1;
+    }
+    if (ndirs > 0)
+        b->kit->ray(d, b->n, par, (const double*)(b->ws + b->L.dirs), ndirs, (const double*)(b->ws + b->L.centers),
+                    (double*)(b->ws + b->L.Lout), b->stream);
+}
+
+hipGraphExec_t batch_graph(lbcg_batch* b, int par, int steps, int ndirs) {
+    for (auto& g : b->graphs)
+        if (g.par == par && g.steps == steps && g.ndirs == ndirs) return g.exec;
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+    batch_chunk(b, par, steps, ndirs);
+    HIPCHK(hipStreamEndCapture(b->stream, &graph));
+    hipGraphExec_t exec;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    HIPCHK(hipGraphDestroy(graph));
+    HIPCHK(e);
+    b->graphs.push_back({exec, par, steps, ndirs});
+    return exec;
+}
+}  // namespace
+
+lbcg_status lbcg_batch_run(lbcg_batch* b, int64_t nsteps, int64_t measure_every, int ndirs, const double* dirs,
+                           double* L_hist, int use_graph) {
+    return guarded([&] {
+        if (!b) throw Error(LBCG_EINVAL, "batch is NULL");
+        if (nsteps < 0 || measure_every < 0) throw Error(LBCG_EINVAL, "nsteps and measure_every must be >= 0");
+        if (measure_every > 1000000) throw Error(LBCG_EINVAL, "measure_every too large");
+        check_dirs(b->p[0].dim, ndirs, dirs);
+        const bool meas = measure_every > 0 && ndirs > 0;
+        if (meas && !L_hist) throw Error(LBCG_EINVAL, "L_hist is NULL");
+        if (use_graph && !b->stream) throw Error(LBCG_EINVAL, "graph replay needs a non-null stream");
+        if (meas)
+            HIPCHK(hipMemcpyAsync(b->ws + b->L.dirs, dirs, sizeof(double) * 3 * ndirs, hipMemcpyHostToDevice, b->stream));
+        const int chunk = (int)(measure_every > 0 ? measure_every : 100);
+        int64_t done = 0, sample = 0;
+        while (done < nsteps) {
+            const int steps = (int)std::min<int64_t>(chunk, nsteps - done);
+            const bool ray = meas && steps == chunk;
+            if (use_graph) HIPCHK(hipGraphLaunch(batch_graph(b, b->par, steps, ray ? ndirs : 0), b->stream));
+            else batch_chunk(b, b->par, steps, ray ? ndirs : 0);
+            HIPCHK(hipGetLastError());
+            if (steps & 1) b->par ^= 1;
+            done += steps;
+            if (ray) {
+                HIPCHK(hipMemcpyAsync(L_hist + sample * (int64_t)b->n * ndirs, b->ws + b->L.Lout,
+                                      sizeof(double) * b->n * ndirs, hipMemcpyDeviceToHost, b->stream));
+                sample++;
+            }
+        }
+        b->nstep += nsteps;
+        HIPCHK(hipStreamSynchronize(b->stream));
+    });
+}
+
+lbcg_status lbcg_batch_measure(lbcg_batch* b, int ndirs, const double* dirs, double* L_out) {
+    return guarded([&] {
+        if (!b) throw Error(LBCG_EINVAL, "batch is NULL");
+        check_dirs(b->p[0].dim, ndirs, dirs);
+        if (ndirs == 0) return;
+        if (!L_out) throw Error(LBCG_EINVAL, "L_out is NULL");
+        HIPCHK(hipMemcpyAsync(b->ws + b->L.dirs, dirs, sizeof(double) * 3 * ndirs, hipMemcpyHostToDevice, b->stream));
+        batch_chunk(b, b->par, 0, ndirs);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(L_out, b->ws + b->L.Lout, sizeof(double) * b->n * ndirs, hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    });
+}
+
+lbcg_status lbcg_batch_read_field(lbcg_batch* b, int inst, int field, void* dst, size_t dst_bytes, int dst_on_device,
+                                  int dst_dtype) {
+    return guarded([&] {
+        if (!b) throw Error(LBCG_EINVAL, "batch is NULL");
+        if (inst < 0 || inst >= b->n) throw Error(LBCG_EINVAL, "instance index out of range");
+        read_field_impl(b->p[inst], b->inst[inst], b->par, b->ws + b->L.staging, b->common, b->stream, field, dst,
+                        dst_bytes, dst_on_device, dst_dtype);
+    });
+}
+
+int64_t lbcg_batch_step_count(const lbcg_batch* b) { return b ? b->nstep : -1; }
+
+lbcg_status lbcg_batch_destroy(lbcg_batch* b) {
+    if (!b) return LBCG_OK;
+    for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    delete b;
     return LBCG_OK;
 }
 

@@ -337,7 +337,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void step_single(InstDev I, int par) {
 
 // Batched launch: the tiles of all instances form one list; each workgroup finds its instance
 // by binary search over the tile offsets.
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ>
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX>
 __global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restrict__ insts, int ninst,
                                                          int par) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -348,7 +348,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restri
         else hi = mid - 1;
     }
     const InstDev I = insts[lo];
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ>(I, t - I.tile_begin, par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX>(I, t - I.tile_begin, par);
 }
 
 }  // namespace lbcg

@@ -73,12 +73,22 @@ def lib():
         L.lbcg_variant_select.argtypes = [vp, i32]
         L.lbcg_variant_time.argtypes = [vp, i32, i32, dp]
         L.lbcg_autotune.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int), dp]
+        L.lbcg_batch_workspace_bytes.argtypes = [i32, pp]
+        L.lbcg_batch_workspace_bytes.restype = sz
+        L.lbcg_batch_create.argtypes = [i32, pp, vp, sz, vp, ctypes.POINTER(vp)]
+        L.lbcg_batch_run.argtypes = [vp, i64, i64, i32, dp, dp, i32]
+        L.lbcg_batch_measure.argtypes = [vp, i32, dp, dp]
+        L.lbcg_batch_read_field.argtypes = [vp, i32, i32, vp, sz, i32, i32]
+        L.lbcg_batch_step_count.argtypes = [vp]
+        L.lbcg_batch_step_count.restype = i64
+        L.lbcg_batch_destroy.argtypes = [vp]
         L.lbcg_last_error.argtypes = []
         L.lbcg_last_error.restype = ctypes.c_char_p
         for name in ("lbcg_create", "lbcg_step", "lbcg_read_field", "lbcg_write_field",
                      "lbcg_measure", "lbcg_growth_rates", "lbcg_destroy", "lbcg_variant_name",
                      "lbcg_variant_select", "lbcg_variant_time", "lbcg_autotune", "lbcg_variant_count",
-                     "lbcg_variant_current"):
+                     "lbcg_variant_current", "lbcg_batch_create", "lbcg_batch_run", "lbcg_batch_measure",
+                     "lbcg_batch_read_field", "lbcg_batch_destroy"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -225,6 +235,73 @@ class Solver:
     def close(self):
         if getattr(self, "handle", None):
             lib().lbcg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent grids of one kind (same dim, flow, precision) stepped together."""
+
+    def __init__(self, plist, precision: str = "fp32", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the lbcg solver needs a HIP device")
+        self.plist = [dict(p) for p in plist]
+        self.n = len(plist)
+        arr = (lbcg_params * self.n)(*[make_params(p, precision) for p in plist])
+        self._params = arr
+        nbytes = int(lib().lbcg_batch_workspace_bytes(self.n, arr))
+        if nbytes == 0:
+            h = ctypes.c_void_p()
+            check(lib().lbcg_batch_create(self.n, arr, None, 0, None, ctypes.byref(h)), "lbcg_batch_create")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        # a stream of its own (default priority): graph capture needs a non-null stream
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.handle = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        check(lib().lbcg_batch_create(self.n, arr, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.handle)),
+              "lbcg_batch_create")
+
+    def run(self, nsteps: int, measure_every: int = 0, dirs=None, use_graph: bool = True):
+        """Returns L_hist [samples, n, ndirs] (None without measurements)."""
+        dirs = np.zeros((0, 3)) if dirs is None else np.ascontiguousarray(dirs, dtype=np.float64)
+        nd = dirs.shape[0]
+        ns = nsteps // measure_every if (measure_every > 0 and nd > 0) else 0
+        L = np.zeros((max(ns, 1), self.n, max(nd, 1)))
+        check(lib().lbcg_batch_run(self.handle, int(nsteps), int(measure_every), nd, _dptr(dirs) if nd else None,
+                                   _dptr(L), 1 if use_graph else 0), "lbcg_batch_run")
+        return L[:ns, :, :nd] if ns else None
+
+    def measure(self, dirs):
+        dirs = np.ascontiguousarray(dirs, dtype=np.float64)
+        L = np.zeros((self.n, dirs.shape[0]))
+        check(lib().lbcg_batch_measure(self.handle, dirs.shape[0], _dptr(dirs), _dptr(L)), "lbcg_batch_measure")
+        return L
+
+    def read(self, i: int, field: str, dtype=np.float64) -> np.ndarray:
+        p = self.plist[i]
+        shape = (int(p["nz"]), int(p["ny"]), int(p["nx"]))
+        qs = 5 if p["dim"] == 2 else 7
+        qf = 9 if p["dim"] == 2 else 19
+        k = {"raw_h": qs, "raw_g": qs, "raw_f": qf}.get(field)
+        out = np.empty(((k,) if k else ()) + shape, dtype=dtype)
+        check(lib().lbcg_batch_read_field(self.handle, int(i), FIELD[field], out.ctypes.data, out.nbytes, 0,
+                                          DTYPE[np.dtype(dtype).type]), "lbcg_batch_read_field")
+        return out
+
+    @property
+    def nstep(self) -> int:
+        return int(lib().lbcg_batch_step_count(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lbcg_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -263,3 +263,46 @@ def test_every_variant_computes_the_same_step(lb, cfg, prec):
         for a, b in zip(state, ref):
             err = np.abs(a - b).max() / np.abs(b).max()
             assert err < (1e-12 if prec == "fp64" else 1e-5), (name, err)
+
+
+# ---- batched sweep ------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_matches_single_instances_bitwise(lb, use_graph):
+    """Each instance of a batch evolves exactly as a single solver with its parameters."""
+    draws = W.sweep_draws(6, seed=7)
+    draws[0] = (64,) + draws[0][1:]
+    plist = [W.sweep_instance(*d) for d in draws]
+    dirs = W.directions(16)
+    b = lb.Batch(plist, "fp32")
+    hist = b.run(300, 100, dirs, use_graph=use_graph)
+    b.run(7)  # an odd remainder without measurements
+    assert hist.shape == (3, len(plist), 16) and b.nstep == 307
+    for i, p in enumerate(plist):
+        s = lb.Solver(p, "fp32")
+        assert s.variants()[s.variant] == "block 64x4x1 nt-stores"  # the batch's tiling
+        Ls = []
+        for _ in range(3):
+            s.step(100)
+            Ls.append(s.measure(dirs)[0])
+        s.step(7)
+        assert np.array_equal(np.array(Ls), hist[:, i, :]), i
+        for f in ("raw_h", "raw_g", "raw_f", "phi_prev"):
+            assert np.array_equal(s.read(f, np.float32), b.read(i, f, np.float32)), (i, f)
+        s.close()
+    b.close()
+
+
+def test_batch_against_oracle(lb, orc):
+    draws = W.sweep_draws(3, seed=11)
+    plist = [W.sweep_instance(min(d[0], 96), *d[1:]) for d in draws]
+    b = lb.Batch(plist, "fp64")
+    b.run(200)
+    for i, p in enumerate(plist):
+        ref = orc.Sim(p)
+        ref.step(200)
+        rf = ref.fields()
+        errs = field_errors(lambda f: b.read(i, f), rf, ("phi", "U", "rho", "ux", "uy"))
+        print(f"[parity] batch instance {i} side {p['nx']}: " + ", ".join(f"{k}={v:.1e}" for k, v in errs.items()))
+        assert max(errs.values()) < 1e-10
+    b.close()
