@@ -94,6 +94,7 @@ def gpu_case(name, p, prec, steps, warmup, with_measure):
     from paper_2206_02145_amd import workloads as W
     nodes = p["nx"] * p["ny"] * p["nz"]
     s = lbcg.Solver(p, prec)
+    variant = s.variants()[s.variant]  # the default tiling (the fastest measured on MI355X)
     dirs = W.directions(16, p["dim"])
     s.step(warmup)
     torch.cuda.synchronize()
@@ -112,9 +113,59 @@ def gpu_case(name, p, prec, steps, warmup, with_measure):
                mlups=nodes * steps / (ms_job * 1e-3) / 1e6,
                kernel_ms=ms_kernel / steps, kernel_mlups=nodes / t_launch / 1e6,
                bytes_per_lup=bpl, achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS,
-               crystal_mean_L=float(L.mean()), nonfinite=mass["nonfinite"])
+               crystal_mean_L=float(L.mean()), nonfinite=mass["nonfinite"], variant=variant)
     log(f"{name}: {out['mlups']:.0f} MLUPS (job), kernel {out['kernel_ms']*1e3:.1f} us/step = "
         f"{achieved:.0f} GB/s algorithmic ({out['frac']*100:.1f}% of {HBM_PEAK_GBS:.0f})")
+    return out
+
+
+def sweep_case(n: int, steps: int, measure_every: int, plain: bool = True):
+    """Batched parametric sweep of n 2-D instances (side, U0, R, u_in drawn from the seeded generator)
+    against the same instances run one after another through the single-grid path."""
+    import numpy as np
+    import torch
+
+    from paper_2206_02145_amd import lbcg
+    from paper_2206_02145_amd import workloads as W
+    plist = [W.sweep_instance(*d) for d in W.sweep_draws(n)]
+    nodes = sum(p["nx"] * p["ny"] for p in plist)
+    dirs = W.directions(16)
+    t0 = time.perf_counter()
+    b = lbcg.Batch(plist, "fp32")
+    t_create = time.perf_counter() - t0
+    b.run(measure_every, measure_every, dirs)  # captures the graph (not timed); a separate batch is timed
+    b.close()
+    del b
+    torch.cuda.synchronize()
+    b = lbcg.Batch(plist, "fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist_b = b.run(steps, measure_every, dirs, use_graph=True)
+    t_batched = time.perf_counter() - t0
+    b.close()
+    del b
+    out = dict(instances=n, steps=steps, measure_every=measure_every, total_nodes=nodes,
+               batched_s=t_batched, batched_runs_per_s=n / t_batched,
+               batched_mlups=nodes * steps / t_batched / 1e6, create_s=t_create)
+    log(f"sweep batched: {n} runs x {steps} steps in {t_batched:.2f} s = {n / t_batched:.1f} runs/s "
+        f"({out['batched_mlups']:.0f} MLUPS)")
+    if plain:
+        t0 = time.perf_counter()
+        hist_p = np.zeros_like(hist_b)
+        for i, p in enumerate(plist):
+            s = lbcg.Solver(p, "fp32")
+            for k in range(steps // measure_every):
+                s.step(measure_every)
+                hist_p[k, i] = s.measure(dirs)[0]
+            s.close()
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        diff = float(np.abs(hist_p - hist_b).max())
+        out.update(plain_s=t_plain, plain_runs_per_s=n / t_plain, speedup=t_plain / t_batched,
+                   max_abs_L_diff_batched_vs_plain=diff)
+        log(f"sweep plain: {t_plain:.2f} s = {n / t_plain:.1f} runs/s; batched speedup {t_plain / t_batched:.1f}x, "
+            f"max |L batched - L plain| = {diff:.1e}")
+    torch.cuda.empty_cache()
     return out
 
 
@@ -228,6 +279,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batched-sweep comparison")
+    ap.add_argument("--sweep-n", type=int, default=256)
+    ap.add_argument("--sweep-steps", type=int, default=4000)
     ap.add_argument("--profile-run", action="store_true",
                     help="a short run of the headline kernel and a 1 GiB copy, for rocprofv3")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -266,6 +320,7 @@ def main():
     head = gpu_case("3-D flow 192x128x128 fp32", p3, "fp32", args.steps, args.warmup, True)
     f16 = gpu_case("3-D flow 192x128x128 fp16shift", p3, "fp16shift", args.steps, args.warmup, False)
     c2 = gpu_case("3-D no-flow 128^3 fp32", W.config2(), "fp32", args.steps, args.warmup, False)
+    sweep = None if args.no_sweep else sweep_case(args.sweep_n, args.sweep_steps, MEASURE_EVERY)
     cpu = None if args.no_cpu else cpu_baseline(p3)
     if cpu:
         log(f"cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads ({cpu['sample']})")
@@ -291,9 +346,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["frac"], 4),
                      "traffic": traffic,
-                     "kernel": "step_single<3, flow, float, float, 32, 4, 4>",
+                     "kernel": "step_single (" + head["variant"] + ")",
                      "bytes_per_lup": head["bytes_per_lup"], "kernel_us": round(head["kernel_ms"] * 1e3, 2)},
         "cpu_baseline": cpu,
+        "sweep": None if sweep is None else {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sweep.items()},
         "variants": {
             "fp16shift_flow": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in f16.items()},
             "no_flow_128cube": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c2.items()},

@@ -265,17 +265,23 @@ const Ops* march_ops(int nx) {
 
 constexpr int MARCH_MAX_NX = 256;
 
+// Non-temporal population stores pay off once the two population copies exceed what the 256 MB
+// last-level (Infinity) cache holds; below that the next step re-reads them from that cache.
+constexpr double LLC_BYTES = 256.0 * 1024 * 1024;
+
 template <int DIM, bool FLOW, typename real, typename fst>
-void block_variants(std::vector<Variant>& v) {
+void block_variants(std::vector<Variant>& v, bool large) {
     auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
     if constexpr (DIM == 2) {
-        // first = default, also the tiling of the batched launch
         static const Ops a = BlockOps<2, FLOW, real, fst, 64, 4, 1, false, sizeof(real) == 8 ? 0 : 2>::ops();
+        static const Ops a0 = BlockOps<2, FLOW, real, fst, 64, 4, 1, false, 0>::ops();
         static const Ops b = BlockOps<2, FLOW, real, fst, 64, 4, 1, true>::ops();
         static const Ops c = BlockOps<2, FLOW, real, fst, 64, 2, 1, true, 2>::ops();
         static const Ops d = BlockOps<2, FLOW, real, fst, 64, 8, 1, false, 2>::ops();
         static const Ops e = BlockOps<2, FLOW, real, fst, 128, 2, 1, false, 2>::ops();
-        for (const Ops* o : {&a, &b, &c, &d, &e}) add(*o);
+        // the batched launch uses the first of these (64 x 4, streaming stores in binary32)
+        if (large || sizeof(real) == 8) for (const Ops* o : {&a, &a0, &b, &c, &d, &e}) add(*o);
+        else for (const Ops* o : {&a0, &a, &b, &c, &d, &e}) add(*o);
     } else if constexpr (sizeof(real) == 8) {
         static const Ops a = BlockOps<3, FLOW, real, fst, 16, 4, 4>::ops();
         static const Ops b = BlockOps<3, FLOW, real, fst, 32, 2, 4, true>::ops();
@@ -293,15 +299,16 @@ void block_variants(std::vector<Variant>& v) {
         static const Ops c0 = BlockOps<3, FLOW, real, fst, 32, 8, 2>::ops();
         static const Ops c1 = BlockOps<3, FLOW, real, fst, 32, 8, 2, true>::ops();
         static const Ops c2 = BlockOps<3, FLOW, real, fst, 32, 4, 4, true>::ops();
-        // first = default: the fastest on the 3-D flow grids measured on MI355X
-        for (const Ops* o : {&a2, &a3, &a0, &a1, &b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
+        // first = default: 64 x 2 x 4 (the fastest measured on MI355X), streaming stores for large grids
+        if (large) for (const Ops* o : {&a2, &a3, &a0, &a1, &b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
+        else for (const Ops* o : {&a0, &a1, &a2, &a3, &b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
     }
 }
 
 template <int DIM, bool FLOW, typename real, typename fst>
-std::vector<Variant> variants_of(int nx) {
+std::vector<Variant> variants_of(int nx, double pop_bytes) {
     std::vector<Variant> v;
-    block_variants<DIM, FLOW, real, fst>(v);
+    block_variants<DIM, FLOW, real, fst>(v, pop_bytes > LLC_BYTES);
     if constexpr (DIM == 3) {
         if (nx <= MARCH_MAX_NX) {
             // z-marching kernel first: the default for 3-D grids with rows of up to 256 nodes
@@ -325,17 +332,24 @@ std::vector<Variant> variants_of(int nx) {
     return v;
 }
 
-std::vector<Variant> variants_for(int dim, int flow, int prec, int nx) {
+// Candidate tilings for one grid kind; the first is the default. pop_bytes: both population copies.
+std::vector<Variant> variants_for(int dim, int flow, int prec, int nx, double pop_bytes) {
+    const double b = pop_bytes;
     if (dim == 2) {
-        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx) : variants_of<2, false, float, float>(nx);
-        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx)
-               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx)
-                                   : variants_of<2, true, float, __half>(nx);
+        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx, b) : variants_of<2, false, float, float>(nx, b);
+        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx, b)
+               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx, b)
+                                   : variants_of<2, true, float, __half>(nx, b);
     }
-    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx) : variants_of<3, false, float, float>(nx);
-    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx)
-           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx)
-                               : variants_of<3, true, float, __half>(nx);
+    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx, b) : variants_of<3, false, float, float>(nx, b);
+    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx, b)
+           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx, b)
+                               : variants_of<3, true, float, __half>(nx, b);
+}
+
+double population_bytes(const lbcg_params& p) {
+    const double N = (double)p.nx * p.ny * p.nz;
+    return 2.0 * N * (2.0 * qs_of(p.dim) * real_size(p.precision) + (p.flow ? qf_of(p.dim) * fstore_size(p.precision) : 0.0));
 }
 
 std::string variant_name(const Variant& v) {
@@ -546,7 +560,7 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
         hdl->L = L;
         hdl->ws = (char*)dev_workspace;
         hdl->stream = (hipStream_t)hip_stream;
-        hdl->variants = variants_for(p->dim, p->flow, p->precision, p->nx);
+        hdl->variants = variants_for(p->dim, p->flow, p->precision, p->nx, population_bytes(*p));
         hdl->variant = 0;
         hdl->ops = hdl->variants[0].ops;
         hdl->inst = make_inst(p, hdl->ws, L, hdl->variants[0].tiling);
@@ -895,7 +909,7 @@ lbcg_status lbcg_batch_create(int n, const lbcg_params* p, void* dev_workspace, 
         b->ws = (char*)dev_workspace;
         b->stream = (hipStream_t)hip_stream;
         b->kit = &batch_kit_for(p[0].dim, p[0].flow, p[0].precision);
-        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx)[0].ops;
+        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0)[0].ops;
         b->par = 0;
         b->nstep = 0;
         int tiles = 0;
