@@ -198,6 +198,35 @@ int64_t lbcg_batch_step_count(const lbcg_batch* b);  /* -1 for NULL */
 /* Release the host state and captured graphs (the workspace stays the caller's). NULL accepted. */
 lbcg_status lbcg_batch_destroy(lbcg_batch* b);
 
+/* ---- Growth-rate surrogate: a multilayer perceptron trained and evaluated on the GPU ----
+ * Layers l = 0 .. nlayers-1 map widths[l] -> widths[l+1]; hidden layers use SiLU, the last layer is
+ * linear and its output is split into a mean head (first half) and a log-variance head (second
+ * half). GEMMs run on bf16 MFMA with fp32 accumulation: weights are kept as fp32 master copies and
+ * used as bf16; activations and back-propagated gradients are rounded to bf16 after their fp32
+ * epilogue. Parameters are packed per layer as W (widths[l+1] x widths[l], row-major) then b. The
+ * loss is the Gaussian negative log-likelihood (1/(B D)) sum 0.5 (exp(-s)(t - mu)^2 + s), with the
+ * log-variance s clamped to [-12, 12]. Device pointers: X (rows x widths[0]), T (rows x D, D =
+ * widths[nlayers]/2), idx (int32, B rows of X/T forming the batch, clamped to [0, rows)). */
+typedef struct lbcg_mlp lbcg_mlp;
+size_t lbcg_mlp_workspace_bytes(int nlayers, const int* widths, int max_batch);  /* 0 if invalid */
+lbcg_status lbcg_mlp_create(int nlayers, const int* widths, int max_batch, void* dev_workspace, size_t bytes,
+                            void* hip_stream, lbcg_mlp** out);                    /* parameters 0 */
+int64_t lbcg_mlp_num_params(const lbcg_mlp* m);
+/* Upload / download fp32 parameters (host, packed); upload resets the Adam state. Synchronise. */
+lbcg_status lbcg_mlp_set_params(lbcg_mlp* m, const float* host_params);
+lbcg_status lbcg_mlp_get_params(lbcg_mlp* m, float* host_params);
+/* Inference: y (device, B x widths[nlayers]) from x (device, B x widths[0]); enqueued only. */
+lbcg_status lbcg_mlp_forward(lbcg_mlp* m, int B, const float* x, float* y);
+/* Loss and gradients of one batch without an update (gradients packed like the parameters, host).
+ * Synchronises. */
+lbcg_status lbcg_mlp_grads(lbcg_mlp* m, int B, const float* X, const float* T, const int* idx, int rows,
+                           float* host_grads, float* loss_out);
+/* One training step: gather, forward, loss, backward, Adam (bias-corrected; the step count is
+ * kept by the handle). *loss_out (may be NULL) gets the batch loss before the update. Synchronises. */
+lbcg_status lbcg_mlp_train_step(lbcg_mlp* m, int B, const float* X, const float* T, const int* idx, int rows,
+                                float lr, float beta1, float beta2, float eps, float* loss_out);
+lbcg_status lbcg_mlp_destroy(lbcg_mlp* m);
+
 /* Message of the calling thread's last error ("" if none). */
 const char* lbcg_last_error(void);
 

@@ -16,6 +16,7 @@
 
 #include "../../include/lbcg.h"
 #include "diag.hpp"
+#include "errors.hpp"
 #include "lattice.hpp"
 #include "march.hpp"
 #include "step.hpp"
@@ -24,7 +25,6 @@ using namespace lbcg;
 
 namespace {
 
-thread_local std::string g_err;
 
 struct Error : std::runtime_error {
     lbcg_status code;
@@ -41,13 +41,13 @@ struct Error : std::runtime_error {
 template <typename F> lbcg_status guarded(F&& fn) {
     try {
         fn();
-        g_err.clear();
+        lbcg::last_error_slot().clear();
         return LBCG_OK;
     } catch (const Error& e) {
-        g_err = e.what();
+        lbcg::last_error_slot() = e.what();
         return e.code;
     } catch (const std::exception& e) {
-        g_err = e.what();
+        lbcg::last_error_slot() = e.what();
         return LBCG_EDEVICE;
     }
 }
@@ -740,7 +740,7 @@ lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* 
         }
     });
     if (st == LBCG_OK && nonfinite) {
-        g_err = "non-finite phi, U or rho found";
+        lbcg::last_error_slot() = "non-finite phi, U or rho found";
         return LBCG_ENONFINITE;
     }
     return st;
@@ -1048,6 +1048,6 @@ lbcg_status lbcg_batch_destroy(lbcg_batch* b) {
     return LBCG_OK;
 }
 
-const char* lbcg_last_error(void) { return g_err.c_str(); }
+const char* lbcg_last_error(void) { return lbcg::last_error_slot().c_str(); }
 
 }  // extern "C"

@@ -82,13 +82,28 @@ def lib():
         L.lbcg_batch_step_count.argtypes = [vp]
         L.lbcg_batch_step_count.restype = i64
         L.lbcg_batch_destroy.argtypes = [vp]
+        L.lbcg_mlp_workspace_bytes.argtypes = [i32, ctypes.POINTER(ctypes.c_int), i32]
+        L.lbcg_mlp_workspace_bytes.restype = sz
+        L.lbcg_mlp_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int), i32, vp, sz, vp, ctypes.POINTER(vp)]
+        L.lbcg_mlp_num_params.argtypes = [vp]
+        L.lbcg_mlp_num_params.restype = i64
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.lbcg_mlp_set_params.argtypes = [vp, fp]
+        L.lbcg_mlp_get_params.argtypes = [vp, fp]
+        L.lbcg_mlp_forward.argtypes = [vp, i32, vp, vp]
+        L.lbcg_mlp_grads.argtypes = [vp, i32, vp, vp, vp, i32, fp, fp]
+        L.lbcg_mlp_train_step.argtypes = [vp, i32, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_float, fp]
+        L.lbcg_mlp_destroy.argtypes = [vp]
         L.lbcg_last_error.argtypes = []
         L.lbcg_last_error.restype = ctypes.c_char_p
         for name in ("lbcg_create", "lbcg_step", "lbcg_read_field", "lbcg_write_field",
                      "lbcg_measure", "lbcg_growth_rates", "lbcg_destroy", "lbcg_variant_name",
                      "lbcg_variant_select", "lbcg_variant_time", "lbcg_autotune", "lbcg_variant_count",
                      "lbcg_variant_current", "lbcg_batch_create", "lbcg_batch_run", "lbcg_batch_measure",
-                     "lbcg_batch_read_field", "lbcg_batch_destroy"):
+                     "lbcg_batch_read_field", "lbcg_batch_destroy", "lbcg_mlp_create", "lbcg_mlp_set_params",
+                     "lbcg_mlp_get_params", "lbcg_mlp_forward", "lbcg_mlp_grads", "lbcg_mlp_train_step",
+                     "lbcg_mlp_destroy"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -302,6 +317,80 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             lib().lbcg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _fptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class MLP:
+    """The surrogate network on the GPU (lbcg_mlp_*): bf16 MFMA GEMMs, fp32 master weights, Adam."""
+
+    def __init__(self, widths, max_batch: int, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the lbcg MLP needs a HIP device")
+        self.widths = [int(w) for w in widths]
+        self.nl = len(self.widths) - 1
+        self._w = (ctypes.c_int * len(self.widths))(*self.widths)
+        self.max_batch = int(max_batch)
+        nbytes = int(lib().lbcg_mlp_workspace_bytes(self.nl, self._w, self.max_batch))
+        if nbytes == 0:
+            raise ValueError("invalid MLP shape")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.handle = ctypes.c_void_p()
+        check(lib().lbcg_mlp_create(self.nl, self._w, self.max_batch, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.handle)),
+              "lbcg_mlp_create")
+        self.n_params = int(lib().lbcg_mlp_num_params(self.handle))
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.n_params
+        check(lib().lbcg_mlp_set_params(self.handle, _fptr(flat)), "lbcg_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        check(lib().lbcg_mlp_get_params(self.handle, _fptr(out)), "lbcg_mlp_get_params")
+        return out
+
+    def forward(self, x_dev, y_dev=None):
+        """x_dev: torch float32 (B, widths[0]) on the device; returns y (B, widths[-1])."""
+        import torch
+        B = int(x_dev.shape[0])
+        if y_dev is None:
+            y_dev = torch.empty((B, self.widths[-1]), dtype=torch.float32, device="cuda")
+        check(lib().lbcg_mlp_forward(self.handle, B, ctypes.c_void_p(x_dev.data_ptr()),
+                                     ctypes.c_void_p(y_dev.data_ptr())), "lbcg_mlp_forward")
+        return y_dev
+
+    def grads(self, X_dev, T_dev, idx_dev):
+        g = np.empty(self.n_params, dtype=np.float32)
+        loss = ctypes.c_float()
+        check(lib().lbcg_mlp_grads(self.handle, int(idx_dev.shape[0]), ctypes.c_void_p(X_dev.data_ptr()),
+                                   ctypes.c_void_p(T_dev.data_ptr()), ctypes.c_void_p(idx_dev.data_ptr()),
+                                   int(X_dev.shape[0]), _fptr(g), ctypes.byref(loss)), "lbcg_mlp_grads")
+        return g, loss.value
+
+    def train_step(self, X_dev, T_dev, idx_dev, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> float:
+        loss = ctypes.c_float()
+        check(lib().lbcg_mlp_train_step(self.handle, int(idx_dev.shape[0]), ctypes.c_void_p(X_dev.data_ptr()),
+                                        ctypes.c_void_p(T_dev.data_ptr()), ctypes.c_void_p(idx_dev.data_ptr()),
+                                        int(X_dev.shape[0]), lr, beta1, beta2, eps, ctypes.byref(loss)),
+              "lbcg_mlp_train_step")
+        return loss.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().lbcg_mlp_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,102 @@
+"""The surrogate's bf16-MFMA MLP kernels (through the C ABI) against the reference MLP, which
+rounds to bf16 at the same points (oracle/mlp.py). Remaining differences come from fp32 vs fp64
+accumulation, and from the rare activation whose bf16 rounding flips because of it."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [4, 256, 256, 256, 64]
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2206_02145_amd import lbcg
+    lbcg.lib()
+    return lbcg
+
+
+def init(widths, seed=0):
+    rng = np.random.default_rng(seed)
+    layers = [(rng.normal(size=(o, i)) / np.sqrt(i), rng.normal(size=o) * 0.1) for i, o in zip(widths[:-1], widths[1:])]
+    return M.pack(layers).astype(np.float32)
+
+
+def data(B, seed=1):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, size=(B, 4))
+    t = np.concatenate([np.sin(2 * x[:, :1] + x[:, 1:2]) * np.arange(1, 33) / 32.0, ], axis=1) + 0.1 * x[:, 2:3]
+    return x.astype(np.float32), t.astype(np.float32)
+
+
+@pytest.mark.parametrize("B", [1, 63, 300])
+def test_forward_matches_reference(lb, B):
+    import torch
+    flat = init(WIDTHS)
+    net = lb.MLP(WIDTHS, 512)
+    net.set_params(flat)
+    assert np.array_equal(net.get_params(), flat)
+    x, _ = data(B)
+    y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy()
+    yr, _ = M.forward(M.unpack(WIDTHS, flat.astype(np.float64)), x.astype(np.float64), bf16=True)
+    err = np.abs(y - yr)
+    print(f"[mlp] forward B={B}: max {err.max() / np.abs(yr).max():.2e}, mean {err.mean() / np.abs(yr).mean():.2e}")
+    assert err.max() <= 5e-3 * np.abs(yr).max() and err.mean() <= 1e-4 * np.abs(yr).mean()
+    net.close()
+
+
+def test_gradients_match_reference(lb):
+    import torch
+    flat = init(WIDTHS, seed=2)
+    net = lb.MLP(WIDTHS, 512)
+    net.set_params(flat)
+    x, t = data(300, seed=3)
+    idx = np.random.default_rng(4).permutation(300)[:257].astype(np.int32)
+    g, loss = net.grads(torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"),
+                        torch.tensor(idx, device="cuda"))
+    lr_, grads = M.loss_and_grads(M.unpack(WIDTHS, flat.astype(np.float64)), x[idx].astype(np.float64),
+                                  t[idx].astype(np.float64), bf16=True)
+    assert abs(loss - lr_) < 1e-5 * abs(lr_)
+    gl = M.unpack(WIDTHS, g.astype(np.float64))
+    for l, ((gW, gb), (rW, rb)) in enumerate(zip(gl, grads)):
+        eW = np.linalg.norm(gW - rW) / np.linalg.norm(rW)
+        eb = np.linalg.norm(gb - rb) / np.linalg.norm(rb)
+        print(f"[mlp] layer {l} grad rel err W {eW:.2e} b {eb:.2e}")
+        assert eW < 1e-2 and eb < 1e-2, l
+    net.close()
+
+
+def test_training_follows_reference_adam(lb):
+    """30 Adam steps on the GPU and in the reference from the same start and batches."""
+    import torch
+    widths = [4, 64, 64, 8]
+    flat = init(widths, seed=5)
+    net = lb.MLP(widths, 256)
+    net.set_params(flat)
+    x, t = data(512, seed=6)
+    t = t[:, :4].copy()
+    X, T = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    opt = M.Adam(flat.size, lr=2e-3)
+    w = flat.astype(np.float64)
+    rng = np.random.default_rng(7)
+    losses = []
+    for k in range(30):
+        idx = rng.permutation(512)[:128].astype(np.int32)
+        lg = net.train_step(X, T, torch.tensor(idx, device="cuda"), lr=2e-3)
+        lr_, grads = M.loss_and_grads(M.unpack(widths, w), x[idx].astype(np.float64), t[idx].astype(np.float64),
+                                      bf16=True)
+        w = opt.step(w, M.pack(grads))
+        losses.append((lg, lr_))
+    wg = net.get_params().astype(np.float64)
+    rel = np.linalg.norm(wg - w) / np.linalg.norm(w - flat)
+    print(f"[mlp] after 30 steps: loss gpu {losses[-1][0]:.4f} ref {losses[-1][1]:.4f}; "
+          f"|w_gpu - w_ref| / |w_ref - w0| = {rel:.2e}")
+    assert abs(losses[-1][0] - losses[-1][1]) < 1e-2 * abs(losses[-1][1]) + 1e-3
+    assert rel < 2e-2
+    assert losses[-1][1] < losses[0][1]
+    net.close()
