@@ -282,6 +282,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched-sweep comparison")
     ap.add_argument("--sweep-n", type=int, default=256)
     ap.add_argument("--sweep-steps", type=int, default=4000)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate study")
+    ap.add_argument("--surrogate-train", type=int, default=4096)
     ap.add_argument("--profile-run", action="store_true",
                     help="a short run of the headline kernel and a 1 GiB copy, for rocprofv3")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -321,6 +323,12 @@ def main():
     f16 = gpu_case("3-D flow 192x128x128 fp16shift", p3, "fp16shift", args.steps, args.warmup, False)
     c2 = gpu_case("3-D no-flow 128^3 fp32", W.config2(), "fp32", args.steps, args.warmup, False)
     sweep = None if args.no_sweep else sweep_case(args.sweep_n, args.sweep_steps, MEASURE_EVERY)
+    surr = None
+    if not args.no_surrogate:
+        from paper_2206_02145_amd import surrogate
+        surr = surrogate.run_study(n_train=args.surrogate_train, log=log)
+        if sweep and "plain_runs_per_s" in sweep:
+            surr["plain_sequential_runs_per_s"] = sweep["plain_runs_per_s"]
     cpu = None if args.no_cpu else cpu_baseline(p3)
     if cpu:
         log(f"cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads ({cpu['sample']})")
@@ -350,6 +358,7 @@ def main():
                      "bytes_per_lup": head["bytes_per_lup"], "kernel_us": round(head["kernel_ms"] * 1e3, 2)},
         "cpu_baseline": cpu,
         "sweep": None if sweep is None else {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sweep.items()},
+        "surrogate": surr,
         "variants": {
             "fp16shift_flow": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in f16.items()},
             "no_flow_128cube": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c2.items()},

@@ -1,0 +1,42 @@
+"""The surrogate end to end at a reduced size: solver-generated data, GPU training, fallback."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def study():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2206_02145_amd import surrogate as S
+    from paper_2206_02145_amd import workloads as W
+    tr = S.generate(W.sweep_draws(768, seed=5), steps=2000)
+    ho = S.generate(W.sweep_draws(96, seed=6), steps=2000)
+    return S, tr, ho
+
+
+def test_dataset_records_growth(study):
+    S, tr, ho = study
+    assert tr.L.shape == (768, 21, 16) and np.isfinite(tr.L).all()
+    # supersaturated seeds grow on average; G is the least-squares slope of L
+    assert tr.G[:, -1].mean() > 0
+    t = tr.t
+    a = int(np.searchsorted(t, t[-1] / 2))
+    G = np.polyfit(t[a:], tr.L[3, a:, 5], 1)[0]
+    assert abs(G - tr.G[3, -1, 5]) < 1e-12
+
+
+def test_surrogate_gains_over_the_solver_alone(study):
+    """Accepted predictions are within the tolerance and the surrogate with fallback answers more
+    runs per second than the batched solver alone."""
+    S, tr, ho = study
+    m = S.Surrogate(with_side=True)
+    info = m.train(tr, steps=2500)
+    res = S.evaluate(m, ho, solve_runs_per_s=len(ho.draws) / ho.solve_s)
+    print("[surrogate]", info, res, flush=True)
+    assert res["accepted"] >= 0.3 * res["held_out"]
+    assert res["accepted_within_tol"] >= 0.9
+    assert res["runs_per_s"] > res["solver_alone_runs_per_s"]
+    m.net.close()
