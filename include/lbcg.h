@@ -145,20 +145,24 @@ lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* 
 lbcg_status lbcg_growth_rates(lbcg_handle* h, double* G_out, double* R2_out, double* G_avg_out);
 
 /* Step-kernel variants: the tilings the library can run for this solver (z-marching over full
- * rows or 3-D blocks, of several shapes). Every variant computes the same update bit for bit;
- * they differ only in speed. Variant 0 is the default. */
+ * rows or 3-D blocks, of several shapes, and their cache policies). Every variant computes the
+ * same update, up to the rounding of floating-point contractions the compiler may choose
+ * differently per tiling; they differ in speed. Variant 0 is the default. */
 int lbcg_variant_count(const lbcg_handle* h);   /* -1 for a NULL handle */
 int lbcg_variant_current(const lbcg_handle* h); /* -1 for a NULL handle */
 lbcg_status lbcg_variant_name(const lbcg_handle* h, int idx, char* buf, size_t buflen);
 lbcg_status lbcg_variant_select(lbcg_handle* h, int idx);
 
-/* Mean launch time (microseconds, HIP events on the handle's stream) of `launches` launches of
- * variant idx on the current state, which is left unchanged (phi_prev is saved in the staging
- * area and restored). Synchronises. */
+/* Mean time per step (microseconds, HIP events on the handle's stream) of `launches` coupled
+ * steps run with variant idx after one untimed step. These are real steps: the state and the
+ * step count advance by launches + 1, as lbcg_step(h, launches + 1) with variant idx selected
+ * would advance them. The selected variant is left as it was.
+ * LBCG_ENONFINITE if the last measurement found a non-finite value. Synchronises. */
 lbcg_status lbcg_variant_time(lbcg_handle* h, int idx, int launches, double* us);
 
 /* Time every variant as lbcg_variant_time does, select the fastest, and return its index and
- * time (either output may be NULL). The state is unchanged. Synchronises. */
+ * time (either output may be NULL). The state advances by (launches + 1) x lbcg_variant_count
+ * steps. Synchronises. */
 lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_us);
 
 /* Release the host handle (the workspace stays the caller's). NULL is accepted. */

@@ -125,6 +125,8 @@ struct Tiling {
     int TX, TY, TZ;
     bool prefetch;  // own populations loaded before the halo barrier
     int aux;        // store cache policy
+    int laux = 0;   // cache policy of the single-use loads (g, f, phi_prev)
+    int zband = 0;  // z tile-layers per band of the block tile order (0: plain x, y, z order)
 };
 
 InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling& T) {
@@ -138,6 +140,7 @@ InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling&
     I.tiles_z = p->dim == 3 ? (p->nz + T.TZ - 1) / T.TZ : 1;
     I.tile_begin = 0;
     I.zc = T.TZ;
+    I.zband = T.march ? 0 : T.zband;
     I.N = (long long)p->nx * p->ny * p->nz;
     for (int k = 0; k < 2; k++) {
         I.h[k] = ws + L.h[k];
@@ -226,15 +229,18 @@ struct CommonOps {
     }
 };
 
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0>
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
+          int LAUX = 0>
 struct BlockOps : CommonOps<DIM, FLOW, real, fst> {
     using C = CommonOps<DIM, FLOW, real, fst>;
     static void step(const InstDev& I, int par, hipStream_t s) {
         const int nblocks = I.tiles_x * I.tiles_y * I.tiles_z;
-        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX>), dim3(nblocks),
+        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX>), dim3(nblocks),
                            dim3(TX * TY * TZ), 0, s, I, par);
     }
-    static Ops ops() { return Ops{Tiling{false, TX, TY, TZ, PF, AUX}, step, C::init, C::field, C::reduce, C::ray}; }
+    static Ops ops() {
+        return Ops{Tiling{false, TX, TY, TZ, PF, AUX, LAUX, 0}, step, C::init, C::field, C::reduce, C::ray};
+    }
 };
 
 template <bool FLOW, typename real, typename fst, int NW, int TY>
@@ -245,7 +251,7 @@ struct MarchOps : CommonOps<3, FLOW, real, fst> {
         hipLaunchKernelGGL((march3d_single<FLOW, real, fst, NW, TY>), dim3(nblocks), dim3(64 * NW * TY), 0, s,
                            I, par, I.zc);
     }
-    static Ops ops() { return Ops{Tiling{true, 64 * NW, TY, 16, true, 0}, step, C::init, C::field, C::reduce, C::ray}; }
+    static Ops ops() { return Ops{Tiling{true, 64 * NW, TY, 16, true, 0, 0, 0}, step, C::init, C::field, C::reduce, C::ray}; }
 };
 
 // A variant = kernel instantiation + tiling (the z-marching kernel takes its plane count at run time).
@@ -299,9 +305,19 @@ void block_variants(std::vector<Variant>& v, bool large) {
         static const Ops c0 = BlockOps<3, FLOW, real, fst, 32, 8, 2>::ops();
         static const Ops c1 = BlockOps<3, FLOW, real, fst, 32, 8, 2, true>::ops();
         static const Ops c2 = BlockOps<3, FLOW, real, fst, 32, 4, 4, true>::ops();
-        // first = default: 64 x 2 x 4 (the fastest measured on MI355X), streaming stores for large grids
-        if (large) for (const Ops* o : {&a2, &a3, &a0, &a1, &b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
-        else for (const Ops* o : {&a0, &a1, &a2, &a3, &b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
+        static const Ops d0 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2>::ops();
+        auto band = [&](const Ops& o, int zband) {  // the same kernel with a banded tile order
+            Tiling t = o.tiling;
+            t.zband = zband;
+            v.push_back({&o, t});
+        };
+        // first = default: 64 x 2 x 4 (one wavefront per x-row); streaming stores when the two
+        // population copies exceed the last-level cache
+        if (large) for (const Ops* o : {&a2, &a3, &a0, &a1}) add(*o);
+        else for (const Ops* o : {&a0, &a1, &a2, &a3}) add(*o);
+        for (int zb : {2, 4, 8}) band(large ? a2 : a0, zb);
+        band(large ? a3 : a1, 4);
+        for (const Ops* o : {&b0, &b1, &b2, &b3, &c0, &c1, &c2, &d0}) add(*o);
     }
 }
 
@@ -311,20 +327,20 @@ std::vector<Variant> variants_of(int nx, double pop_bytes) {
     block_variants<DIM, FLOW, real, fst>(v, pop_bytes > LLC_BYTES);
     if constexpr (DIM == 3) {
         if (nx <= MARCH_MAX_NX) {
-            // z-marching kernel first: the default for 3-D grids with rows of up to 256 nodes
+            // z-marching kernels (rows of up to 256 nodes) as further candidates
             const int zcs[] = {8, 16, 4, 32};
             for (int zc : zcs) {
                 const Ops* o = march_ops<FLOW, real, fst, 2>(nx);
-                v.push_back({o, Tiling{true, o->tiling.TX, 2, zc, true, 0}});
+                v.push_back({o, Tiling{true, o->tiling.TX, 2, zc, true, 0, 0, 0}});
             }
             for (int zc : zcs) {
                 const Ops* o = march_ops<FLOW, real, fst, 1>(nx);
-                v.push_back({o, Tiling{true, o->tiling.TX, 1, zc, true, 0}});
+                v.push_back({o, Tiling{true, o->tiling.TX, 1, zc, true, 0, 0, 0}});
             }
             if constexpr (sizeof(real) == 4) {
                 for (int zc : zcs) {
                     const Ops* o = march_ops<FLOW, real, fst, 4>(nx);
-                    v.push_back({o, Tiling{true, o->tiling.TX, 4, zc, true, 0}});
+                    v.push_back({o, Tiling{true, o->tiling.TX, 4, zc, true, 0, 0, 0}});
                 }
             }
         }
@@ -358,8 +374,9 @@ std::string variant_name(const Variant& v) {
     if (t.march)
         std::snprintf(buf, sizeof buf, "march rows=%d x %d planes (row %d)", t.TY, t.TZ, t.TX);
     else
-        std::snprintf(buf, sizeof buf, "block %dx%dx%d%s%s", t.TX, t.TY, t.TZ, t.prefetch ? " prefetch" : "",
-                      t.aux ? " nt-stores" : "");
+        std::snprintf(buf, sizeof buf, "block %dx%dx%d%s%s%s", t.TX, t.TY, t.TZ, t.prefetch ? " prefetch" : "",
+                      t.aux ? " nt-stores" : "", t.laux ? " nt-loads" : "");
+        if (t.zband > 1) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " zband %d", t.zband);
     return buf;
 }
 
@@ -419,7 +436,7 @@ struct BatchImpl {
         hipLaunchKernelGGL((raymarch_batch_kernel<DIM, real>), dim3(ndirs, n), dim3(64), 0, s, d, par, dirs, ndirs,
                            centers, out);
     }
-    static BatchKit kit() { return BatchKit{Tiling{false, TX, TY, TZ, PF, AUX}, step, ray}; }
+    static BatchKit kit() { return BatchKit{Tiling{false, TX, TY, TZ, PF, AUX, 0, 0}, step, ray}; }
 };
 
 const BatchKit& batch_kit_for(int dim, int flow, int prec) {
@@ -812,30 +829,32 @@ void select_variant(lbcg_handle* h, int idx) {
     h->variant = idx;
 }
 
-// Mean launch time of variant idx on the current state, which it leaves unchanged: the kernel
-// reads the current buffers and writes the other ones; phi_prev, updated in place, is saved to
-// the staging area and restored.
+// Times real coupled steps with variant idx: one untimed step, then `launches` timed ones, with the
+// ping-pong parity alternating as in lbcg_step (re-reading one input copy would let the
+// last-level cache hold part of it and flatter the variant). The state advances by launches + 1
+// steps of variant idx.
 double time_variant(lbcg_handle* h, int idx, int launches) {
+    if (h->nonfinite) throw Error(LBCG_ENONFINITE, "the last measurement found a non-finite value");
     const int keep = h->variant;
     select_variant(h, idx);
-    const size_t pbytes = (size_t)h->inst.N * real_size(h->p.precision);
-    void* stage = h->ws + h->L.staging;
-    HIPCHK(hipMemcpyAsync(stage, h->inst.phi_prev, pbytes, hipMemcpyDeviceToDevice, h->stream));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     h->ops->step(h->inst, h->par, h->stream);  // warm-up
+    h->par ^= 1;
     HIPCHK(hipEventRecord(e0, h->stream));
-    for (int k = 0; k < launches; k++) h->ops->step(h->inst, h->par, h->stream);
+    for (int k = 0; k < launches; k++) {
+        h->ops->step(h->inst, h->par, h->stream);
+        h->par ^= 1;
+    }
     HIPCHK(hipEventRecord(e1, h->stream));
+    h->nstep += launches + 1;
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     HIPCHK(hipEventDestroy(e0));
     HIPCHK(hipEventDestroy(e1));
-    HIPCHK(hipMemcpyAsync(h->inst.phi_prev, stage, pbytes, hipMemcpyDeviceToDevice, h->stream));
-    HIPCHK(hipStreamSynchronize(h->stream));
     select_variant(h, keep);
     return 1e3 * (double)ms / launches;
 }

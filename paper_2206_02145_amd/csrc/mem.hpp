@@ -45,8 +45,8 @@ template <> struct BufOps<__half> {
 };
 
 // q planes of N values of storage type T; loads convert to the compute type R. Stores use the
-// cache-policy bits AUX.
-template <typename T, int AUX = 0> struct Planes {
+// cache-policy bits AUX, loads LAUX.
+template <typename T, int AUX = 0, int LAUX = 0> struct Planes {
     const char* base;
     unsigned plane_bytes;  // N * sizeof(T), < 2^32
 
@@ -58,9 +58,9 @@ template <typename T, int AUX = 0> struct Planes {
     }
     template <typename R> __device__ __forceinline__ R ld(int a, unsigned node) const {
         if constexpr (std::is_same<T, __half>::value)
-            return (R)__half2float(BufOps<T>::template ld<0>(rsrc(a), node * 2u));
+            return (R)__half2float(BufOps<T>::template ld<LAUX>(rsrc(a), node * 2u));
         else
-            return (R)BufOps<T>::template ld<0>(rsrc(a), node * (unsigned)sizeof(T));
+            return (R)BufOps<T>::template ld<LAUX>(rsrc(a), node * (unsigned)sizeof(T));
     }
     template <typename R> __device__ __forceinline__ void st(int a, unsigned node, R v) const {
         if constexpr (std::is_same<T, __half>::value)

@@ -49,7 +49,8 @@ namespace lbcg {
 struct InstDev {
     int nx, ny, nz, xopen;
     int tiles_x, tiles_y, tiles_z, tile_begin;
-    int zc, pad_;                 // planes per workgroup of the z-marching kernel
+    int zc;                       // planes per workgroup of the z-marching kernel
+    int zband;                    // block tiles: z tile-layers per band of the tile order (<= 1: none)
     long long N;                  // nodes
     void* h[2];                   // ping-pong population arrays, planes [a][z][y][x]
     void* g[2];
@@ -96,7 +97,15 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 
 // PF: issue the own node's g, f and phi_prev loads before the barrier, so that their latency
 // overlaps the halo load of h. AUX: cache-policy bits of the population stores (0, or 2 = stream).
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0>
+// LAUX: cache-policy bits of the loads of g, f and phi_prev, which are read once (h keeps the
+// default policy: its halo is read again by the neighbouring tiles).
+//
+// Tile order: x fastest, so that the x-neighbours, which share the halo's cache lines, run
+// together. With I.zband = B > 1 the z tile-layers are grouped in bands of B: within a band the
+// order is x, then z, then y, so the tiles above and below run B * tiles_x apart instead of a whole
+// layer apart and the z-halo of h is still in L2 when it is read again.
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
+          int LAUX = 0>
 __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, const int par) {
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
@@ -112,14 +121,25 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     const long long N = I.N;
     const int tix = tile % I.tiles_x;
     const int trest = tile / I.tiles_x;
-    const int tiy = trest % I.tiles_y;
-    const int tiz = trest / I.tiles_y;
+    int tiy, tiz;
+    if (I.zband <= 1) {
+        tiy = trest % I.tiles_y;
+        tiz = trest / I.tiles_y;
+    } else {
+        const int per_band = I.tiles_y * I.zband;
+        const int band = trest / per_band;
+        const int q = trest - band * per_band;
+        const int rem = I.tiles_z - band * I.zband;  // the last band may be partial
+        const int bz = rem < I.zband ? rem : I.zband;
+        tiz = band * I.zband + q % bz;
+        tiy = q / bz;
+    }
     const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
 
     const Planes<real, AUX> hin(I.h[par], N), hout(I.h[par ^ 1], N);
-    const Planes<real, AUX> gin(I.g[par], N), gout(I.g[par ^ 1], N);
-    const Planes<real> pprev(I.phi_prev, N);
-    const Planes<fst, AUX> fin(I.f[par], N), fout(I.f[par ^ 1], N);
+    const Planes<real, AUX, LAUX> gin(I.g[par], N), gout(I.g[par ^ 1], N);
+    const Planes<real, 0, LAUX> pprev(I.phi_prev, N);
+    const Planes<fst, AUX, LAUX> fin(I.f[par], N), fout(I.f[par ^ 1], N);
 
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
     const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
@@ -330,14 +350,14 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     pprev.st(0, gi, psi);
 }
 
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX>
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX>
 __global__ __launch_bounds__(TX* TY* TZ) void step_single(InstDev I, int par) {
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX>(I, xcd_tile(blockIdx.x, gridDim.x), par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX>(I, xcd_tile(blockIdx.x, gridDim.x), par);
 }
 
 // Batched launch: the tiles of all instances form one list; each workgroup finds its instance
 // by binary search over the tile offsets.
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX>
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX = 0>
 __global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restrict__ insts, int ninst,
                                                          int par) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -348,7 +368,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restri
         else hi = mid - 1;
     }
     const InstDev I = insts[lo];
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX>(I, t - I.tile_begin, par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX>(I, t - I.tile_begin, par);
 }
 
 }  // namespace lbcg

@@ -237,11 +237,14 @@ class Solver:
         check(lib().lbcg_variant_select(self.handle, int(idx)), "lbcg_variant_select")
 
     def time_variant(self, idx: int, launches: int = 20) -> float:
+        """Microseconds per step of variant idx over `launches` real steps (the state advances by
+        launches + 1 steps)."""
         us = ctypes.c_double()
         check(lib().lbcg_variant_time(self.handle, int(idx), int(launches), ctypes.byref(us)), "lbcg_variant_time")
         return us.value
 
     def autotune(self, launches: int = 20):
+        """Select the fastest variant; the state advances by (launches + 1) steps per variant."""
         best = ctypes.c_int()
         us = ctypes.c_double()
         check(lib().lbcg_autotune(self.handle, int(launches), ctypes.byref(best), ctypes.byref(us)), "lbcg_autotune")

@@ -265,6 +265,26 @@ def test_every_variant_computes_the_same_step(lb, cfg, prec):
             assert err < (1e-12 if prec == "fp64" else 1e-5), (name, err)
 
 
+def test_variant_timer_runs_real_steps(lb):
+    """Timing a variant advances the state by launches + 1 steps of that variant and leaves the
+    selected variant alone."""
+    p = W.scaled(W.config3(), 70, 20, 18, seed_R=6.0)
+    a, b = lb.Solver(p, "fp32"), lb.Solver(p, "fp32")
+    k = len(a.variants()) - 1
+    a.step(3)
+    us = a.time_variant(k, 4)
+    assert us > 0 and a.nstep == 8 and a.variant == 0
+    b.step(3)
+    b.select_variant(k)
+    b.step(5)
+    for f in ("raw_h", "raw_g", "raw_f", "phi_prev"):
+        assert np.array_equal(a.read(f), b.read(f)), f
+    best, best_us = a.autotune(2)
+    assert a.variant == best and best_us > 0 and a.nstep == 8 + 3 * len(a.variants())
+    a.close()
+    b.close()
+
+
 # ---- batched sweep ------------------------------------------------------------------------------
 
 @pytest.mark.parametrize("use_graph", [True, False])
