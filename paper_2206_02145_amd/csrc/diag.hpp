@@ -23,8 +23,8 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev I, int par, SeedArgs 
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
     const long long N = I.N;
-    const Planes<real> h(I.h[par], N), g(I.g[par], N), pp(I.phi_prev, N);
-    const Planes<fst> f(I.f[par], N);
+    const Planes<real> h(pick(I.h, par), N), g(pick(I.g, par), N), pp(I.phi_prev, N);
+    const Planes<fst> f(pick(I.f, par), N);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % I.nx);
@@ -61,7 +61,7 @@ __device__ inline void node_moments(const InstDev& I, int par, long long i, real
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
     const long long N = I.N;
-    const Planes<real> h(I.h[par], N), g(I.g[par], N);
+    const Planes<real> h(pick(I.h, par), N), g(pick(I.g, par), N);
     const int x = (int)(i % I.nx);
     const unsigned row = (unsigned)(i - x);
     psi = 0;
@@ -75,7 +75,7 @@ __device__ inline void node_moments(const InstDev& I, int par, long long i, real
     rho = 1;
     usx = usy = usz = 0;
     if constexpr (FLOW) {
-        const Planes<fst> f(I.f[par], N);
+        const Planes<fst> f(pick(I.f, par), N);
         real drho = 0, mx = 0, my = 0, mz = 0;
 #pragma unroll
         for (int a = 0; a < V::Q; a++) {
@@ -246,7 +246,7 @@ template <int DIM, typename real>
 __device__ inline void raymarch_one(const InstDev& I, int par, const double* dv_in, const double* c_in,
                                     double* L_out) {
     const int lane = threadIdx.x;
-    const real* h = static_cast<const real*>(I.h[par]);
+    const real* h = static_cast<const real*>(pick(I.h, par));
     const double ds = 0.25;
     const double c[3] = {c_in[0], c_in[1], DIM == 3 ? c_in[2] : 0.0};
     const double dv[3] = {dv_in[0], dv_in[1], DIM == 3 ? dv_in[2] : 0.0};

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/lbcg.h"
@@ -313,7 +314,9 @@ void block_variants(std::vector<Variant>& v, bool large) {
         };
         // first = default: 64 x 2 x 4 (one wavefront per x-row); streaming stores when the two
         // population copies exceed the last-level cache
-        if (large) for (const Ops* o : {&a2, &a3, &a0, &a1}) add(*o);
+        // (binary16 flow storage: with the own populations prefetched before the halo barrier)
+        if (large && std::is_same<fst, __half>::value) for (const Ops* o : {&a3, &a2, &a0, &a1}) add(*o);
+        else if (large) for (const Ops* o : {&a2, &a3, &a0, &a1}) add(*o);
         else for (const Ops* o : {&a0, &a1, &a2, &a3}) add(*o);
         for (int zb : {2, 4, 8}) band(large ? a2 : a0, zb);
         band(large ? a3 : a1, 4);

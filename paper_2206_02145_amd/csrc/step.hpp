@@ -62,15 +62,9 @@ struct InstDev {
     double u_in, U_in, U0;
 };
 
-// Population storage type: the compute type, or binary16 (deviation stored round-to-nearest-even).
-template <typename real, typename st> struct Store {
-    __device__ static inline real ld(const st* p, long long i) { return p[i]; }
-    __device__ static inline void st_(st* p, long long i, real v) { p[i] = v; }
-};
-template <> struct Store<float, __half> {
-    __device__ static inline float ld(const __half* p, long long i) { return __half2float(p[i]); }
-    __device__ static inline void st_(__half* p, long long i, float v) { p[i] = __float2half_rn(v); }
-};
+// Copy `par` of a ping-pong pair. A select, not an index: indexing a local copy of the record
+// with a run-time value would move the record into private (scratch) memory.
+__host__ __device__ __forceinline__ void* pick(void* const (&a)[2], int par) { return par ? a[1] : a[0]; }
 
 // Memory column of node column x for a population with x-velocity cx (see the layout note).
 __host__ __device__ __forceinline__ int xmem(int x, int cx, int nx) {
@@ -136,10 +130,10 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     }
     const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
 
-    const Planes<real, AUX> hin(I.h[par], N), hout(I.h[par ^ 1], N);
-    const Planes<real, AUX, LAUX> gin(I.g[par], N), gout(I.g[par ^ 1], N);
+    const Planes<real, AUX> hin(pick(I.h, par), N), hout(pick(I.h, par ^ 1), N);
+    const Planes<real, AUX, LAUX> gin(pick(I.g, par), N), gout(pick(I.g, par ^ 1), N);
     const Planes<real, 0, LAUX> pprev(I.phi_prev, N);
-    const Planes<fst, AUX, LAUX> fin(I.f[par], N), fout(I.f[par ^ 1], N);
+    const Planes<fst, AUX, LAUX> fin(pick(I.f, par), N), fout(pick(I.f, par ^ 1), N);
 
     const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
     const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
@@ -364,10 +358,18 @@ __global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restri
     int lo = 0, hi = ninst - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (insts[mid].tile_begin <= t) lo = mid;
+        if (__builtin_amdgcn_readfirstlane(insts[mid].tile_begin) <= t) lo = mid;
         else hi = mid - 1;
     }
-    const InstDev I = insts[lo];
+    // The record is the same for the whole workgroup: read it word by word into scalar registers,
+    // so that the buffer descriptors and the grid constants stay scalar as in the one-grid kernel.
+    static_assert(sizeof(InstDev) % 4 == 0, "InstDev is read as 32-bit words");
+    unsigned w[sizeof(InstDev) / 4];
+    const unsigned* src = reinterpret_cast<const unsigned*>(insts + lo);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(InstDev) / 4); k++) w[k] = __builtin_amdgcn_readfirstlane(src[k]);
+    InstDev I;
+    __builtin_memcpy(&I, w, sizeof(InstDev));
     step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX>(I, t - I.tile_begin, par);
 }
 
