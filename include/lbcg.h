@@ -165,6 +165,26 @@ lbcg_status lbcg_variant_time(lbcg_handle* h, int idx, int launches, double* us)
  * steps. Synchronises. */
 lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_us);
 
+/* ---- Checkpoints ----
+ * The solver state exactly as stored: the current copy of h, g, f (if flow) and phi_prev in the
+ * storage precision and memory layout, after a 64-byte header (magic "LBCGSTAT", format version,
+ * dim, nx, ny, nz, flow, precision, boundary kind, step count). Loading it into a solver with the
+ * same grid, flow, precision and boundary kind continues the run bit for bit, which a round trip
+ * through lbcg_read_field / lbcg_write_field cannot promise (the stored deviations from the lattice
+ * weights may be too small for the decoded binary64 value to carry them). */
+
+/* Bytes of a checkpoint of this solver (0 for a NULL handle). */
+size_t lbcg_state_bytes(const lbcg_handle* h);
+
+/* Copy the state into dst (>= lbcg_state_bytes; device pointer if dst_on_device, else host
+ * memory). ENOMEM if dst is too small. Synchronises. */
+lbcg_status lbcg_state_save(lbcg_handle* h, void* dst, size_t dst_bytes, int dst_on_device);
+
+/* Replace the state (and the step count) with a checkpoint. EINVAL if the header does not match
+ * this solver; ENOMEM if src_bytes is short. Clears the non-finite flag; the crystal-size history
+ * of lbcg_measure is kept. Synchronises. */
+lbcg_status lbcg_state_load(lbcg_handle* h, const void* src, size_t src_bytes, int src_on_device);
+
 /* Release the host handle (the workspace stays the caller's). NULL is accepted. */
 lbcg_status lbcg_destroy(lbcg_handle* h);
 

@@ -160,6 +160,20 @@ InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling&
     I.u_in = p->u_inlet;
     I.U_in = p->U_inlet;
     I.U0 = p->U0;
+    const double inv_cs2 = p->dim == 3 ? 4.0 : 3.0;  // D3Q7 / D2Q5
+    I.kd[K_EPS] = I.eps;
+    I.kd[K_GEPS2] = I.grad_eps2;
+    I.kd[K_KC] = I.k * inv_cs2;
+    I.kd[K_LAMBDA] = I.lambda;
+    I.kd[K_ITAU0] = I.inv_tau0;
+    I.kd[K_U0] = I.U0;
+    I.kd[K_KDRAG] = I.kdrag;
+    I.kd[K_ITAUF] = 1.0 / I.tau_f;
+    I.kd[K_GUO] = 1.0 - 0.5 / I.tau_f;
+    I.kd[K_UIN] = I.u_in;
+    I.kd[K_DQ] = I.D * inv_cs2;
+    I.kd[K_UIN2] = 2.0 * (I.U_in - I.U0);
+    for (int k = 0; k < 12; k++) I.kf[k] = (float)I.kd[k];
     return I;
 }
 
@@ -894,6 +908,97 @@ lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_
         select_variant(h, bi);
         if (best) *best = bi;
         if (best_us) *best_us = bt;
+    });
+}
+
+// ---- checkpoints ----
+
+namespace {
+struct StateHeader {
+    char magic[8];
+    int32_t version, dim, nx, ny, nz, flow, precision, xbc;
+    int64_t nstep;
+    char pad[16];
+};
+static_assert(sizeof(StateHeader) == 64, "checkpoint header is 64 bytes");
+constexpr char STATE_MAGIC[8] = {'L', 'B', 'C', 'G', 'S', 'T', 'A', 'T'};
+
+// (offset in the workspace, bytes) of each stored array of the current copy, in blob order
+std::vector<std::pair<size_t, size_t>> state_parts(const lbcg_handle* h) {
+    const lbcg_params& p = h->p;
+    const size_t N = (size_t)h->inst.N, rs = real_size(p.precision), fs = fstore_size(p.precision);
+    std::vector<std::pair<size_t, size_t>> v;
+    v.push_back({h->L.h[h->par], qs_of(p.dim) * N * rs});
+    v.push_back({h->L.g[h->par], qs_of(p.dim) * N * rs});
+    if (p.flow) v.push_back({h->L.f[h->par], qf_of(p.dim) * N * fs});
+    v.push_back({h->L.phi_prev, N * rs});
+    return v;
+}
+
+size_t state_bytes_of(const lbcg_handle* h) {
+    size_t b = sizeof(StateHeader);
+    for (const auto& q : state_parts(h)) b += q.second;
+    return b;
+}
+}  // namespace
+
+size_t lbcg_state_bytes(const lbcg_handle* h) { return h ? state_bytes_of(h) : 0; }
+
+lbcg_status lbcg_state_save(lbcg_handle* h, void* dst, size_t dst_bytes, int dst_on_device) {
+    return guarded([&] {
+        if (!h || !dst) throw Error(LBCG_EINVAL, "NULL handle or destination");
+        if (dst_bytes < state_bytes_of(h)) throw Error(LBCG_ENOMEM, "destination smaller than lbcg_state_bytes");
+        StateHeader H{};
+        std::memcpy(H.magic, STATE_MAGIC, 8);
+        H.version = 1;
+        H.dim = h->p.dim;
+        H.nx = h->p.nx;
+        H.ny = h->p.ny;
+        H.nz = h->p.nz;
+        H.flow = h->p.flow;
+        H.precision = h->p.precision;
+        H.xbc = h->p.xbc;
+        H.nstep = h->nstep;
+        char* out = static_cast<char*>(dst);
+        if (dst_on_device) HIPCHK(hipMemcpyAsync(out, &H, sizeof H, hipMemcpyHostToDevice, h->stream));
+        else std::memcpy(out, &H, sizeof H);
+        size_t off = sizeof H;
+        for (const auto& q : state_parts(h)) {
+            HIPCHK(hipMemcpyAsync(out + off, h->ws + q.first, q.second,
+                                  dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+            off += q.second;
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
+lbcg_status lbcg_state_load(lbcg_handle* h, const void* src, size_t src_bytes, int src_on_device) {
+    return guarded([&] {
+        if (!h || !src) throw Error(LBCG_EINVAL, "NULL handle or source");
+        if (src_bytes < state_bytes_of(h)) throw Error(LBCG_ENOMEM, "source smaller than lbcg_state_bytes");
+        const char* in = static_cast<const char*>(src);
+        StateHeader H{};
+        if (src_on_device) {
+            HIPCHK(hipMemcpyAsync(&H, in, sizeof H, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        } else {
+            std::memcpy(&H, in, sizeof H);
+        }
+        if (std::memcmp(H.magic, STATE_MAGIC, 8) != 0 || H.version != 1)
+            throw Error(LBCG_EINVAL, "not a checkpoint of this library (magic or version)");
+        if (H.dim != h->p.dim || H.nx != h->p.nx || H.ny != h->p.ny || H.nz != h->p.nz || H.flow != h->p.flow ||
+            H.precision != h->p.precision || H.xbc != h->p.xbc)
+            throw Error(LBCG_EINVAL, "checkpoint of a different grid, lattice set, precision or boundary kind");
+        if (H.nstep < 0) throw Error(LBCG_EINVAL, "negative step count in the checkpoint");
+        size_t off = sizeof H;
+        for (const auto& q : state_parts(h)) {
+            HIPCHK(hipMemcpyAsync(h->ws + q.first, in + off, q.second,
+                                  src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+            off += q.second;
+        }
+        HIPCHK(hipStreamSynchronize(h->stream));
+        h->nstep = H.nstep;
+        h->nonfinite = false;
     });
 }
 

@@ -222,13 +222,22 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
                                  s_hh[hsl][3][row - 1][x],
                                  hn[5],
                                  hmz};
+            real hk[S::Q];
+            real hsum = 0;
 #pragma unroll
             for (int a = 0; a < S::Q; a++) {
                 const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
                 const real wa = (real)S::w(a);
                 const real cN = (real)cx * Nx + (real)cy * Ny + (real)cz * Nz;
                 const real heq = wa * (psi - cN * kc);
-                const real hs = hc[a] - (hc[a] - heq) * inv_tau_phi + wa * Qs;
+                hk[a] = hc[a] - (hc[a] - heq) * inv_tau_phi + wa * Qs;
+                if (a) hsum += hk[a];
+            }
+            hk[0] = (psi + Qs) - hsum;  // rest population from the exact zeroth moment psi + Q/tau0
+#pragma unroll
+            for (int a = 0; a < S::Q; a++) {
+                const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
+                const real hs = hk[a];
                 const unsigned drow = node(0, wrapy(y + cy), wrapz(z + cz));
                 if (cx < 0 && xopen && x == 0) {  // inlet: bounce-back into the opposite slot, old value of that slot
                     const int b = S::opp(a);
@@ -262,6 +271,8 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
                 usz = hs_ * uz;
                 const real uu = usx * usx + usy * usy + usz * usz;
                 const real uF = usx * Fx + usy * Fy + usz * Fz;
+                real fk[V::Q];
+                real fsum = 0;
 #pragma unroll
                 for (int a = 0; a < V::Q; a++) {
                     const int cx = V::c(a, 0), cy = V::c(a, 1), cz = V::c(a, 2);
@@ -270,7 +281,15 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
                     const real cF = (real)cx * Fx + (real)cy * Fy + (real)cz * Fz;
                     const real feq = wa * (drho + rho * ((real)3 * cu + (real)4.5 * cu * cu - (real)1.5 * uu));
                     const real Sa = wa * guo * ((real)3 * cF + (real)9 * cu * cF - (real)3 * uF);
-                    const real fs = fv[a] - (fv[a] - feq) * inv_tau_f + Sa;
+                    fk[a] = fv[a] - (fv[a] - feq) * inv_tau_f + Sa;
+                    if (a) fsum += fk[a];
+                }
+                fk[0] = drho - fsum;  // mass of the node, rho - 1
+#pragma unroll
+                for (int a = 0; a < V::Q; a++) {
+                    const int cx = V::c(a, 0), cy = V::c(a, 1), cz = V::c(a, 2);
+                    const real wa = (real)V::w(a);
+                    const real fs = fk[a];
                     const unsigned drow = node(0, wrapy(y + cy), wrapz(z + cz));
                     if (cx < 0 && xopen && x == 0) {  // inlet: velocity bounce-back, wall density 1
                         const int b = V::opp(a);
@@ -288,13 +307,23 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
                 q = q < (real)0 ? (real)0 : (q > (real)2 ? (real)2 : q);
                 const real inv_tau_U = (real)1 / (DU * q + (real)0.5);
                 const real dphi = psi - pp;
+                real gk[S::Q];
+                real gsum = 0;
 #pragma unroll
                 for (int a = 0; a < S::Q; a++) {
                     const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
                     const real wa = (real)S::w(a);
                     const real cu = (real)cx * usx + (real)cy * usy + (real)cz * usz;
                     const real geq = wa * (Ut + U * cu * (real)S::inv_cs2);
-                    const real gs = gv[a] - (gv[a] - geq) * inv_tau_U - wa * dphi;
+                    gk[a] = gv[a] - (gv[a] - geq) * inv_tau_U - wa * dphi;
+                    if (a) gsum += gk[a];
+                }
+                gk[0] = (Ut - dphi) - gsum;  // solute balance of the node
+#pragma unroll
+                for (int a = 0; a < S::Q; a++) {
+                    const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
+                    const real wa = (real)S::w(a);
+                    const real gs = gk[a];
                     const unsigned drow = node(0, wrapy(y + cy), wrapz(z + cz));
                     if (cx < 0 && xopen && x == 0) {  // inlet: anti-bounce-back, U = U_in on the wall
                         const int b = S::opp(a);

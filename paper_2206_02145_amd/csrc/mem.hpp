@@ -18,29 +18,36 @@ constexpr int BUF_RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, gfx9 family
 
 template <typename T> struct BufOps;
 // AUX: cache-policy bits of the access (0 = default; 2 = non-temporal / streaming).
+// off: per-lane byte offset (VGPR); soff: byte offset shared by the wavefront (SGPR).
 template <> struct BufOps<float> {
-    template <int AUX = 0> __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+    template <int AUX = 0>
+    __device__ static inline float ld(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff = 0) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, AUX));
     }
-    template <int AUX = 0> __device__ static inline void st(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, AUX);
+    template <int AUX = 0>
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, unsigned off, float v, unsigned soff = 0) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, soff, AUX);
     }
 };
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 template <> struct BufOps<double> {
-    template <int AUX = 0> __device__ static inline double ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
-        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+    template <int AUX = 0>
+    __device__ static inline double ld(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff = 0) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, AUX));
     }
-    template <int AUX = 0> __device__ static inline void st(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, AUX);
+    template <int AUX = 0>
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, unsigned off, double v, unsigned soff = 0) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, soff, AUX);
     }
 };
 template <> struct BufOps<__half> {
-    template <int AUX = 0> __device__ static inline __half ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
-        return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX));
+    template <int AUX = 0>
+    __device__ static inline __half ld(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned soff = 0) {
+        return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, AUX));
     }
-    template <int AUX = 0> __device__ static inline void st(__amdgpu_buffer_rsrc_t r, unsigned off, __half v) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, AUX);
+    template <int AUX = 0>
+    __device__ static inline void st(__amdgpu_buffer_rsrc_t r, unsigned off, __half v, unsigned soff = 0) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, soff, AUX);
     }
 };
 
@@ -67,6 +74,22 @@ template <typename T, int AUX = 0, int LAUX = 0> struct Planes {
             BufOps<T>::template st<AUX>(rsrc(a), node * 2u, __float2half_rn((float)v));
         else
             BufOps<T>::template st<AUX>(rsrc(a), node * (unsigned)sizeof(T), (T)v);
+    }
+    // Node row + col where `row` is the same for the whole wavefront: it travels in the scalar
+    // offset of the buffer instruction, and the lane supplies only its column.
+    template <typename R> __device__ __forceinline__ R ldr(int a, unsigned row, unsigned col) const {
+        constexpr unsigned B = sizeof(T);
+        if constexpr (std::is_same<T, __half>::value)
+            return (R)__half2float(BufOps<T>::template ld<LAUX>(rsrc(a), col * B, row * B));
+        else
+            return (R)BufOps<T>::template ld<LAUX>(rsrc(a), col * B, row * B);
+    }
+    template <typename R> __device__ __forceinline__ void str(int a, unsigned row, unsigned col, R v) const {
+        constexpr unsigned B = sizeof(T);
+        if constexpr (std::is_same<T, __half>::value)
+            BufOps<T>::template st<AUX>(rsrc(a), col * B, __float2half_rn((float)v), row * B);
+        else
+            BufOps<T>::template st<AUX>(rsrc(a), col * B, (T)v, row * B);
     }
 };
 

@@ -60,7 +60,30 @@ struct InstDev {
     double inv_tau0, lambda, eps, grad_eps2, D;
     double tau_f, kdrag;          // kdrag = h_drag tau_f / (4 W0^2)
     double u_in, U_in, U0;
+    // Constants of the fused step, derived once on the host in binary64 and rounded to binary32
+    // (the kernel reads those of its precision); indices K_*.
+    double kd[12];
+    float kf[12];
 };
+
+enum : int {
+    K_EPS = 0,    // anisotropy strength eps
+    K_GEPS2,      // |grad phi|^2 threshold of the anisotropy
+    K_KC,         // (W0^2 / tau0) / cs^2 of the phase-field / solute lattice
+    K_LAMBDA,     // coupling constant lambda
+    K_ITAU0,      // 1 / tau0
+    K_U0,         // reference supersaturation U0 (g is stored as g - w U0)
+    K_KDRAG,      // h_drag tau_f / (4 W0^2)
+    K_ITAUF,      // 1 / tau_f
+    K_GUO,        // 1 - 1 / (2 tau_f)
+    K_UIN,        // inlet velocity
+    K_DQ,         // D / cs^2
+    K_UIN2,       // 2 (U_in - U0), the anti-bounce-back term
+};
+template <typename real> __device__ __forceinline__ real kconst(const InstDev& I, int k) {
+    if constexpr (sizeof(real) == 4) return I.kf[k];
+    else return I.kd[k];
+}
 
 // Copy `par` of a ping-pong pair. A select, not an index: indexing a local copy of the record
 // with a run-time value would move the record into private (scratch) memory.
@@ -107,6 +130,10 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     constexpr int BX = TX + 2, BY = TY + 2, BZ = (DIM == 3) ? TZ + 2 : 1;
     constexpr int NB = BX * BY * BZ;
     constexpr int SY = BX, SZ = BX * BY;  // LDS strides
+    // One wavefront per x-row segment: its y and z are the same in every lane, so row offsets are
+    // scalar (computed by the scalar unit, passed in the buffer instructions' scalar offset) and a
+    // lane's address arithmetic reduces to its column.
+    constexpr bool ROW = (TX == 64);
     __shared__ real s_phi[NB];
     __shared__ real s_h[S::Q][NB];
 
@@ -134,48 +161,103 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     const Planes<real, AUX, LAUX> gin(pick(I.g, par), N), gout(pick(I.g, par ^ 1), N);
     const Planes<real, 0, LAUX> pprev(I.phi_prev, N);
     const Planes<fst, AUX, LAUX> fin(pick(I.f, par), N), fout(pick(I.f, par ^ 1), N);
+    // node (row + col) of plane a; with ROW the row is wave-uniform
+    auto LD = [&](const auto& P, int a, unsigned row, int col) -> real {
+        if constexpr (ROW) return P.template ldr<real>(a, row, (unsigned)col);
+        else return P.template ld<real>(a, row + (unsigned)col);
+    };
+    auto ST = [&](const auto& P, int a, unsigned row, int col, real v) {
+        if constexpr (ROW) P.str(a, row, (unsigned)col, v);
+        else P.st(a, row + (unsigned)col, v);
+    };
 
-    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int lx = tid % TX;
+    int lyz = tid / TX;
+    if constexpr (ROW) lyz = __builtin_amdgcn_readfirstlane(lyz);
+    const int ly = lyz % TY, lz = lyz / TY;
     const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-    const bool valid = x < nx && y < ny && z < nz;
-    const int xv = valid ? x : 0;
-    const unsigned rowO = valid ? (unsigned)((z * ny + y) * nx) : 0u;  // own row
-    const unsigned gi = rowO + (unsigned)xv;
+    const bool row_ok = y < ny && z < nz;
+    const bool valid = row_ok && x < nx;
+    const int xv = x < nx ? x : 0;
+    const unsigned rowO = row_ok ? (unsigned)((z * ny + y) * nx) : 0u;  // own row
+    // memory columns of this node for populations with c_x = 0, +1, -1 (x-shifted layout)
+    const int xc0 = xv, xcp = xmem(xv, 1, nx), xcm = xmem(xv, -1, nx);
+    auto xcol = [&](int cx) { return cx > 0 ? xcp : (cx < 0 ? xcm : xc0); };
     real gv[S::Q];
     real fv[V::Q];
     real pp = 0;
     auto load_own = [&]() {
 #pragma unroll
-        for (int a = 0; a < S::Q; a++) gv[a] = gin.template ld<real>(a, rowO + xmem(xv, S::c(a, 0), nx));
+        for (int a = 0; a < S::Q; a++) gv[a] = LD(gin, a, rowO, xcol(S::c(a, 0)));
         if constexpr (FLOW) {
 #pragma unroll
-            for (int a = 0; a < V::Q; a++)
-                fv[a] = fin.template ld<real>(a, rowO + xmem(xv, V::c(a, 0), nx));  // f - w
+            for (int a = 0; a < V::Q; a++) fv[a] = LD(fin, a, rowO, xcol(V::c(a, 0)));  // f - w
         }
-        pp = pprev.template ld<real>(0, gi);
+        pp = LD(pprev, 0, rowO, xc0);
     };
     if constexpr (PF) load_own();
 
     // ---- phase 1: h and phi on the tile + halo ----
-    for (int b = tid; b < NB; b += NT) {
-        const int bx = b % BX;
-        const int br = b / BX;
-        const int by = br % BY;
-        const int bz = br / BY;
+    auto box_x = [&](int bx) {  // grid column of box column bx; at an open face the ghost is the face node
         int gx = x0 + bx - 1;
-        if (I.xopen) gx = gx < 0 ? 0 : (gx > nx - 1 ? nx - 1 : gx);  // ghost = face node
+        if (I.xopen) gx = gx < 0 ? 0 : (gx > nx - 1 ? nx - 1 : gx);
         else gx = wrap_coord(gx, nx);
-        const int gy = wrap_coord(y0 + by - 1, ny);
-        const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
-        const unsigned rb = (unsigned)((gz * ny + gy) * nx);
-        real phi = 0;
+        return gx;
+    };
+    if constexpr (ROW) {
+        // box rows are dealt to the wavefronts; lane l loads box column l, lanes 0 and 1 also 64 + l
+        constexpr int NW = NT / 64;
+        const int ga = box_x(lx), gb = box_x(64 + (lx & 1));
+        const int ca[3] = {ga, xmem(ga, 1, nx), xmem(ga, -1, nx)};
+        const int cb[3] = {gb, xmem(gb, 1, nx), xmem(gb, -1, nx)};
+        auto csel = [](const int* c, int cx) { return cx > 0 ? c[1] : (cx < 0 ? c[2] : c[0]); };
+        for (int r = lyz; r < BY * BZ; r += NW) {
+            const int by = r % BY, bz = r / BY;
+            const int gy = wrap_coord(y0 + by - 1, ny);
+            const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
+            const unsigned rb = (unsigned)((gz * ny + gy) * nx);
+            {
+                const int b = r * BX + lx;
+                real phi = 0;
 #pragma unroll
-        for (int a = 0; a < S::Q; a++) {
-            const real v = hin.template ld<real>(a, rb + xmem(gx, S::c(a, 0), nx));
-            s_h[a][b] = v;
-            phi += v;
+                for (int a = 0; a < S::Q; a++) {
+                    const real v = LD(hin, a, rb, csel(ca, S::c(a, 0)));
+                    s_h[a][b] = v;
+                    phi += v;
+                }
+                s_phi[b] = phi;
+            }
+            if (lx < 2) {
+                const int b = r * BX + 64 + lx;
+                real phi = 0;
+#pragma unroll
+                for (int a = 0; a < S::Q; a++) {
+                    const real v = LD(hin, a, rb, csel(cb, S::c(a, 0)));
+                    s_h[a][b] = v;
+                    phi += v;
+                }
+                s_phi[b] = phi;
+            }
         }
-        s_phi[b] = phi;
+    } else {
+        for (int b = tid; b < NB; b += NT) {
+            const int bx = b % BX;
+            const int br = b / BX;
+            const int by = br % BY;
+            const int bz = br / BY;
+            const int gx = box_x(bx);
+            const int gy = wrap_coord(y0 + by - 1, ny);
+            const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
+            const unsigned rb = (unsigned)((gz * ny + gy) * nx);
+            real phi = 0;
+#pragma unroll
+            for (int a = 0; a < S::Q; a++) {
+                const real v = LD(hin, a, rb, xmem(gx, S::c(a, 0), nx));
+                s_h[a][b] = v;
+                phi += v;
+            }
+            s_phi[b] = phi;
+        }
     }
     __syncthreads();
 
@@ -184,21 +266,27 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     if constexpr (!PF) load_own();
     const int bo = (DIM == 3 ? (lz + 1) * SZ : 0) + (ly + 1) * SY + (lx + 1);
 
-    // neighbour coordinates; -1 marks "through the inlet", nx marks "through the outlet"
+    // Push targets. Every population is written at memory column x of its destination row, except
+    // at an open x face: the inlet node (x = 0) pushes nothing with c_x < 0 (those slots are
+    // bounced back into the opposite populations of the same node) and the outlet node
+    // (x = nx - 1) nothing with c_x > 0; the outlet also copies its c_x < 0 values into the
+    // populations entering through the outlet (memory column 0). Those boundary stores come after
+    // each collision loop, apart from the regular pushes.
     const bool xopen = I.xopen != 0;
-    const int xp = (x + 1 < nx) ? x + 1 : (xopen ? nx : 0);
-    const int xm = (x > 0) ? x - 1 : (xopen ? -1 : nx - 1);
+    const bool at_inlet = xopen && x == 0;
+    const bool at_outlet = xopen && x == nx - 1 && !at_inlet;
+    const bool push_p = !(xopen && x == nx - 1);  // c_x > 0 allowed
+    const bool push_m = !at_inlet;                 // c_x < 0 allowed
+    auto push_ok = [&](int cx) { return cx == 0 || (cx > 0 ? push_p : push_m); };
     const int yp = (y + 1 < ny) ? y + 1 : 0;
     const int ym = (y > 0) ? y - 1 : ny - 1;
     const int zp = (DIM == 3) ? ((z + 1 < nz) ? z + 1 : 0) : 0;
     const int zm = (DIM == 3) ? ((z > 0) ? z - 1 : nz - 1) : 0;
-    auto dst_x = [&](int cx) { return cx > 0 ? xp : (cx < 0 ? xm : x); };
     auto row = [&](int cy, int cz) -> unsigned {
         const int yy = cy > 0 ? yp : (cy < 0 ? ym : y);
         const int zz = cz > 0 ? zp : (cz < 0 ? zm : z);
         return (unsigned)((zz * ny + yy) * nx);
     };
-    const bool at_outlet = xopen && (x == nx - 1);
 
     const real psi = s_phi[bo];  // phi + 1
     const real phi = psi - (real)1;
@@ -217,10 +305,10 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     }
 
     // anisotropy a_s = 1 + eps Re((nx + i ny)^6) and its flux N = 2 eps a_s |p| (grad P - 6 P n)
-    const real eps = (real)I.eps;
+    const real eps = kconst<real>(I, K_EPS);
     real as = 1, Nx = 0, Ny = 0, Nz = 0;
     const real s2 = px * px + py * py + pz * pz;
-    if (s2 > (real)I.grad_eps2) {
+    if (s2 > kconst<real>(I, K_GEPS2)) {
         const real m = sqrt(s2);
         const real im = (real)1 / m;
         const real ux_ = px * im, uy_ = py * im, uz_ = pz * im;
@@ -242,14 +330,16 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     real Ut = 0;
 #pragma unroll
     for (int a = 0; a < S::Q; a++) Ut += gv[a];
-    const real U = Ut + (real)I.U0;
+    const real U = Ut + kconst<real>(I, K_U0);
 
     // ---- phase field: Eq. (d) with the equilibrium of Eq. (e) ----
     {
-        const real kc = (real)(I.k * S::inv_cs2);  // (W0^2/tau0)/cs^2
+        const real kc = kconst<real>(I, K_KC);  // (W0^2/tau0)/cs^2
         const real inv_tau_phi = (real)1 / (a2 * kc + (real)0.5);
         // Q = phi - phi^3 + lambda U (1 - phi^2)^2 = (1 - phi^2)(phi + lambda U (1 - phi^2))
-        const real Qs = p2 * (phi + (real)I.lambda * U * p2) * (real)I.inv_tau0;
+        const real Qs = p2 * (phi + kconst<real>(I, K_LAMBDA) * U * p2) * kconst<real>(I, K_ITAU0);
+        real hk[S::Q], vk[S::Q];  // post-collision values; pushed values (c_x < 0 ones reused at the open faces)
+        real hsum = 0;
 #pragma unroll
         for (int a = 0; a < S::Q; a++) {
             const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
@@ -257,17 +347,29 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             const real cN = (real)cx * Nx + (real)cy * Ny + (real)cz * Nz;
             const real heq = wa * (psi - cN * kc);  // h_eq + w
             const real ha = s_h[a][bo];
-            const real hs = ha - (ha - heq) * inv_tau_phi + wa * Qs;
-            const int xd = dst_x(cx);
-            if (xd >= 0 && xd < nx) {
-                const real hnb = s_h[a][bo + cx + cy * SY + (DIM == 3 ? cz * SZ : 0)];
-                const real v = (hs - one_m_a2 * hnb) * inv_a2;
-                hout.st(a, row(cy, cz) + x, v);  // memory column of node x + cx is x
-                if (cx < 0 && at_outlet) hout.st(a, row(cy, cz) + xmem(x, cx, nx), v);
-            } else if (xd < 0) {  // inlet: bounce back into the opposite slot of this node
-                const int b = S::opp(a);
-                const real v = (hs - one_m_a2 * s_h[b][bo]) * inv_a2;
-                hout.st(b, rowO + xmem(x, S::c(b, 0), nx), v);
+            hk[a] = ha - (ha - heq) * inv_tau_phi + wa * Qs;
+            if (a) hsum += hk[a];
+        }
+        // The collision's zeroth moment is psi + Q/tau0 exactly; taking the rest population from it
+        // keeps each node's phase balance closed in the working precision (in binary32 this stops
+        // a drift of the interface that would otherwise grow linearly with the step count).
+        hk[0] = (psi + Qs) - hsum;
+#pragma unroll
+        for (int a = 0; a < S::Q; a++) {
+            const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
+            const real hnb = s_h[a][bo + cx + cy * SY + (DIM == 3 ? cz * SZ : 0)];
+            vk[a] = (hk[a] - one_m_a2 * hnb) * inv_a2;
+            if (push_ok(cx)) ST(hout, a, row(cy, cz), x, vk[a]);  // memory column of node x + cx is x
+        }
+        if (xopen) {
+#pragma unroll
+            for (int a = 0; a < S::Q; a++) {
+                if (S::c(a, 0) >= 0) continue;
+                if (at_inlet) {  // bounce back into the opposite slot of this node (old value of that slot)
+                    const int b = S::opp(a);
+                    ST(hout, b, rowO, xcp, (hk[a] - one_m_a2 * s_h[b][bo]) * inv_a2);
+                }
+                if (at_outlet) ST(hout, a, row(S::c(a, 1), S::c(a, 2)), xcm, vk[a]);
             }
         }
     }
@@ -284,7 +386,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             if (DIM == 3 && V::c(a, 2)) mz += (real)V::c(a, 2) * fv[a];
         }
         const real rho = (real)1 + drho;
-        const real K = (real)I.kdrag * psi * psi * two_m_psi;  // (1+phi)^2 (1-phi)
+        const real K = kconst<real>(I, K_KDRAG) * psi * psi * two_m_psi;  // (1+phi)^2 (1-phi)
         const real iden = (real)1 / (rho + (real)0.5 * K);
         const real ux = mx * iden, uy = my * iden, uz = mz * iden;
         const real Fx = -K * ux, Fy = -K * uy, Fz = -K * uz;
@@ -294,9 +396,11 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         usz = hs_ * uz;
         const real uu = usx * usx + usy * usy + usz * usz;
         const real uF = usx * Fx + usy * Fy + usz * Fz;
-        const real inv_tau_f = (real)(1.0 / I.tau_f);
-        const real guo = (real)(1.0 - 0.5 / I.tau_f);
-        const real uinx = (real)I.u_in;
+        const real inv_tau_f = kconst<real>(I, K_ITAUF);
+        const real guo = kconst<real>(I, K_GUO);
+        const real uinx = kconst<real>(I, K_UIN);
+        real fk[V::Q];
+        real fsum = 0;
 #pragma unroll
         for (int a = 0; a < V::Q; a++) {
             const int cx = V::c(a, 0), cy = V::c(a, 1), cz = V::c(a, 2);
@@ -306,14 +410,21 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             // f_eq - w = w [rho - 1 + rho (cu/cs2 + cu^2/(2 cs2^2) - uu/(2 cs2))]
             const real feq = wa * (drho + rho * ((real)3 * cu + (real)4.5 * cu * cu - (real)1.5 * uu));
             const real Sa = wa * guo * ((real)3 * cF + (real)9 * cu * cF - (real)3 * uF);
-            const real fs = fv[a] - (fv[a] - feq) * inv_tau_f + Sa;
-            const int xd = dst_x(cx);
-            if (xd >= 0 && xd < nx) {
-                fout.st(a, row(cy, cz) + x, fs);
-                if (cx < 0 && at_outlet) fout.st(a, row(cy, cz) + xmem(x, cx, nx), fs);
-            } else if (xd < 0) {  // velocity bounce-back, wall density 1
-                const int b = V::opp(a);
-                fout.st(b, rowO + xmem(x, V::c(b, 0), nx), fs - (real)6 * wa * (real)cx * uinx);
+            fk[a] = fv[a] - (fv[a] - feq) * inv_tau_f + Sa;
+            if (a) fsum += fk[a];
+        }
+        fk[0] = drho - fsum;  // mass: the collision and the Guo term leave sum_a (f_a - w_a) = rho - 1
+#pragma unroll
+        for (int a = 0; a < V::Q; a++)
+            if (push_ok(V::c(a, 0))) ST(fout, a, row(V::c(a, 1), V::c(a, 2)), x, fk[a]);
+        if (xopen) {
+#pragma unroll
+            for (int a = 0; a < V::Q; a++) {
+                const int cx = V::c(a, 0);
+                if (cx >= 0) continue;
+                if (at_inlet)  // velocity bounce-back, wall density 1
+                    ST(fout, V::opp(a), rowO, xcp, fk[a] - (real)6 * (real)V::w(a) * (real)cx * uinx);
+                if (at_outlet) ST(fout, a, row(V::c(a, 1), V::c(a, 2)), xcm, fk[a]);
             }
         }
     }
@@ -322,26 +433,35 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     {
         real q = two_m_psi;  // 1 - phi, clamped to [0, 2]
         q = q < (real)0 ? (real)0 : (q > (real)2 ? (real)2 : q);
-        const real inv_tau_U = (real)1 / ((real)(I.D * S::inv_cs2) * q + (real)0.5);
+        const real inv_tau_U = (real)1 / (kconst<real>(I, K_DQ) * q + (real)0.5);
         const real dphi = psi - pp;
-        const real Uin2 = (real)2 * (real)(I.U_in - I.U0);
+        const real Uin2 = kconst<real>(I, K_UIN2);
+        real gk[S::Q];
+        real gsum = 0;
 #pragma unroll
         for (int a = 0; a < S::Q; a++) {
             const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
             const real wa = (real)S::w(a);
             const real cu = (real)cx * usx + (real)cy * usy + (real)cz * usz;
             const real geq = wa * (Ut + U * cu * (real)S::inv_cs2);  // g_eq - w U0
-            const real gs = gv[a] - (gv[a] - geq) * inv_tau_U - wa * dphi;
-            const int xd = dst_x(cx);
-            if (xd >= 0 && xd < nx) {
-                gout.st(a, row(cy, cz) + x, gs);
-                if (cx < 0 && at_outlet) gout.st(a, row(cy, cz) + xmem(x, cx, nx), gs);
-            } else if (xd < 0) {  // anti-bounce-back, U = U_in on the inlet wall
-                gout.st(S::opp(a), rowO + xmem(x, S::c(S::opp(a), 0), nx), -gs + wa * Uin2);
+            gk[a] = gv[a] - (gv[a] - geq) * inv_tau_U - wa * dphi;
+            if (a) gsum += gk[a];
+        }
+        gk[0] = (Ut - dphi) - gsum;  // solute balance of the node: sum_a g*_a - U0 = U - U0 - dphi
+#pragma unroll
+        for (int a = 0; a < S::Q; a++)
+            if (push_ok(S::c(a, 0))) ST(gout, a, row(S::c(a, 1), S::c(a, 2)), x, gk[a]);
+        if (xopen) {
+#pragma unroll
+            for (int a = 0; a < S::Q; a++) {
+                if (S::c(a, 0) >= 0) continue;
+                if (at_inlet)  // anti-bounce-back, U = U_in on the inlet wall
+                    ST(gout, S::opp(a), rowO, xcp, -gk[a] + (real)S::w(a) * Uin2);
+                if (at_outlet) ST(gout, a, row(S::c(a, 1), S::c(a, 2)), xcm, gk[a]);
             }
         }
     }
-    pprev.st(0, gi, psi);
+    ST(pprev, 0, rowO, xc0, psi);
 }
 
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX>

@@ -67,6 +67,10 @@ def lib():
         L.lbcg_measure.argtypes = [vp, i32, dp, dp, dp]
         L.lbcg_growth_rates.argtypes = [vp, dp, dp, dp]
         L.lbcg_destroy.argtypes = [vp]
+        L.lbcg_state_bytes.argtypes = [vp]
+        L.lbcg_state_bytes.restype = sz
+        L.lbcg_state_save.argtypes = [vp, vp, sz, i32]
+        L.lbcg_state_load.argtypes = [vp, vp, sz, i32]
         L.lbcg_variant_count.argtypes = [vp]
         L.lbcg_variant_current.argtypes = [vp]
         L.lbcg_variant_name.argtypes = [vp, i32, ctypes.c_char_p, sz]
@@ -103,7 +107,7 @@ def lib():
                      "lbcg_variant_current", "lbcg_batch_create", "lbcg_batch_run", "lbcg_batch_measure",
                      "lbcg_batch_read_field", "lbcg_batch_destroy", "lbcg_mlp_create", "lbcg_mlp_set_params",
                      "lbcg_mlp_get_params", "lbcg_mlp_forward", "lbcg_mlp_grads", "lbcg_mlp_train_step",
-                     "lbcg_mlp_destroy"):
+                     "lbcg_mlp_destroy", "lbcg_state_save", "lbcg_state_load"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -199,6 +203,28 @@ class Solver:
             arr = arr.astype(np.float64)
         check(lib().lbcg_write_field(self.handle, FIELD[field], arr.ctypes.data, arr.nbytes, 0,
                                      DTYPE[arr.dtype.type]), "lbcg_write_field")
+
+    # ---- checkpoints ----
+    def save_state(self, device: bool = False):
+        """The stored state and step count as a uint8 numpy array (host) or torch tensor (device)."""
+        n = int(lib().lbcg_state_bytes(self.handle))
+        if device:
+            import torch
+            out = torch.empty(n, dtype=torch.uint8, device="cuda")
+            check(lib().lbcg_state_save(self.handle, ctypes.c_void_p(out.data_ptr()), n, 1), "lbcg_state_save")
+            return out
+        out = np.empty(n, dtype=np.uint8)
+        check(lib().lbcg_state_save(self.handle, out.ctypes.data, n, 0), "lbcg_state_save")
+        return out
+
+    def load_state(self, blob):
+        """Restore a state written by save_state (numpy array or device tensor)."""
+        if isinstance(blob, np.ndarray):
+            blob = np.ascontiguousarray(blob, dtype=np.uint8)
+            check(lib().lbcg_state_load(self.handle, blob.ctypes.data, blob.nbytes, 0), "lbcg_state_load")
+        else:
+            check(lib().lbcg_state_load(self.handle, ctypes.c_void_p(blob.data_ptr()), blob.numel(), 1),
+                  "lbcg_state_load")
 
     def measure(self, dirs=None, raise_nonfinite: bool = True):
         """(L [ndirs], mass dict) -- see lbcg_measure."""

@@ -169,10 +169,12 @@ def growth_error(G_pred, G_true, floor):
     return np.abs(G_pred - G_true).max(axis=-1) / np.maximum(G_true.mean(axis=-1), floor)
 
 
-def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = None,
-             solve_runs_per_s: float = None, criterion: str = "max_dir"):
+def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = None, criterion: str = "max_dir"):
     """Predict the final growth rates of held-out draws, accept those whose predicted error is
     within tol, and fall back to the solver for the rest (timed with the batched solver).
+
+    The solver alone is timed on all held-out draws just before the fallback, so that both run in
+    the same state of the device and its allocator.
 
     criterion "max_dir": error = max_k |G_pred,k - G_k| / mean_k G_k (every direction);
     criterion "avg": error = |mean_k G_pred,k - mean_k G_k| / mean_k G_k (the average growth rate
@@ -182,6 +184,9 @@ def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = 
     if floor is None:
         floor = 0.1 * float(np.abs(held.G[:, -1]).mean())
     t_end = held.t[-1:]
+    all_draws = [tuple(d) for d in held.draws]
+    steps, every = int(held.t[-1]), int(held.t[1] - held.t[0])
+    t_alone = generate(all_draws, steps=steps, every=every).solve_s
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, _, Gm, Gs = model.predict(held.draws, t_end)
@@ -202,7 +207,7 @@ def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = 
     n_fb = int((~accept).sum())
     t_fb = 0.0
     if n_fb:  # the rejected draws through the batched solver: their results are the solver's
-        t_fb = generate([tuple(d) for d in held.draws[~accept]]).solve_s
+        t_fb = generate([tuple(d) for d in held.draws[~accept]], steps=steps, every=every).solve_s
     err_final = np.where(accept, true_err, 0.0)
     total = t_infer + t_fb
     q = lambda v: None if v is None else round(float(v), 5)
@@ -212,7 +217,7 @@ def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = 
                 accepted_err_mean=q(true_err[accept].mean()) if accept.any() else None,
                 accepted_within_tol=q((true_err[accept] <= tol).mean()) if accept.any() else None,
                 all_err_median=q(np.median(true_err)), all_err_p90=q(np.quantile(true_err, 0.9)),
-                delivered_err_max=q(err_final.max()), solver_alone_runs_per_s=solve_runs_per_s)
+                delivered_err_max=q(err_final.max()), solver_alone_runs_per_s=n / t_alone)
 
 
 def run_study(n_train: int = 4096, n_held: int = 256, steps: int = 4000, train_steps: int = 4000, log=None,
@@ -229,11 +234,11 @@ def run_study(n_train: int = 4096, n_held: int = 256, steps: int = 4000, train_s
                            ("four_inputs_max_dir", False, "max_dir")):
         m = Surrogate(with_side=ws)
         info = m.train(tr, steps=train_steps)
-        res = evaluate(m, ho, solve_runs_per_s=solver_rps, criterion=crit)
+        res = evaluate(m, ho, criterion=crit)
         res.update(train_s=info["train_s"], final_loss=info["final_loss"], inputs=5 if ws else 4)
         out[name] = res
         if log:
             log(f"surrogate {name}: accepted {res['accepted']}/{n_held}, accepted err max {res['accepted_err_max']}, "
-                f"median err {res['all_err_median']}, {res['runs_per_s']:.0f} runs/s vs solver {solver_rps:.0f}")
+                f"median err {res['all_err_median']}, {res['runs_per_s']:.0f} runs/s vs solver {res['solver_alone_runs_per_s']:.0f}")
         m.net.close()
     return out

@@ -200,25 +200,58 @@ def test_solute_plus_solid_invariant_fp32(lb):
 
 # ---- state handling --------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16shift"])
-def test_checkpoint_restart_and_determinism_bitwise(lb, prec):
+@pytest.mark.parametrize("prec,device", [("fp32", False), ("fp16shift", True), ("fp64", False)])
+def test_checkpoint_restart_and_determinism_bitwise(lb, prec, device):
     p = W.scaled(W.config3(), 48, 32, 32, seed_R=6.0)
     a = lb.Solver(p, prec)
     a.step(40)
-    ck = {k: a.read(k, np.float64) for k in ("raw_h", "raw_g", "raw_f", "phi_prev")}
+    ck = a.save_state(device=device)
     a.step(30)
     b = lb.Solver(p, prec)
-    for k, v in ck.items():
-        b.write(k, v)
+    b.step(3)
+    b.load_state(ck)
+    assert b.nstep == 40
     b.step(30)
     c = lb.Solver(p, prec)
     c.step(70)
     for k in ("raw_h", "raw_g", "raw_f", "phi_prev"):
-        ra = a.read(k, np.float32)
-        assert np.array_equal(ra, b.read(k, np.float32)), k   # restart from a checkpoint
-        assert np.array_equal(ra, c.read(k, np.float32)), k   # a second run
+        ra = a.read(k, np.float64)
+        assert np.array_equal(ra, b.read(k, np.float64)), k   # restart from a checkpoint
+        assert np.array_equal(ra, c.read(k, np.float64)), k   # a second run
     for s in (a, b, c):
         s.close()
+
+
+def test_checkpoint_rejects_another_grid(lb):
+    p = W.scaled(W.config3(), 48, 32, 32, seed_R=6.0)
+    a = lb.Solver(p, "fp32")
+    ck = a.save_state()
+    for q, prec in ((W.scaled(W.config3(), 48, 32, 30, seed_R=6.0), "fp32"), (p, "fp16shift")):
+        b = lb.Solver(q, prec)
+        with pytest.raises(lb.LbcgError) as e:
+            b.load_state(ck)
+        assert e.value.status == "EINVAL"
+        b.close()
+    with pytest.raises(lb.LbcgError) as e:
+        a.load_state(ck[:-1])
+    assert e.value.status == "ENOMEM"
+    a.close()
+
+
+def test_raw_population_round_trip(lb):
+    """Writing back what lbcg_read_field returns reproduces the populations to the storage
+    precision (binary32 here: a few units in the last place of each plane)."""
+    p = W.scaled(W.config3(), 40, 24, 20, seed_R=5.0)
+    a = lb.Solver(p, "fp32")
+    a.step(20)
+    b = lb.Solver(p, "fp32")
+    for k in ("raw_h", "raw_g", "raw_f", "phi_prev"):
+        v = a.read(k, np.float64)
+        b.write(k, v)
+        d = np.abs(b.read(k, np.float64) - v).max()
+        assert d <= 2.0 ** -22 * np.abs(v).max(), (k, d)  # stored values are at most twice the decoded scale
+    a.close()
+    b.close()
 
 
 def test_nonfinite_is_reported(lb):

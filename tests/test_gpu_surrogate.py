@@ -34,7 +34,7 @@ def test_surrogate_gains_over_the_solver_alone(study):
     S, tr, ho = study
     m = S.Surrogate(with_side=True)
     info = m.train(tr, steps=2500)
-    res = S.evaluate(m, ho, solve_runs_per_s=len(ho.draws) / ho.solve_s)
+    res = S.evaluate(m, ho)
     print("[surrogate]", info, res, flush=True)
     assert res["accepted"] >= 0.3 * res["held_out"]
     assert res["accepted_within_tol"] >= 0.9
