@@ -183,9 +183,24 @@ def cpu_baseline(p, budget_s: float = 15.0):
     s.step(n)
     dt = time.time() - t0
     nodes = p["nx"] * p["ny"] * p["nz"]
-    return dict(value=nodes * n / dt / 1e6, unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{n} coupled steps of the full {p['nx']}x{p['ny']}x{p['nz']} grid after 1 warm-up "
-                       f"step ({dt:.1f} s, FP64)")
+    out = dict(value=nodes * n / dt / 1e6, unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+               sample=f"{n} coupled steps of the full {p['nx']}x{p['ny']}x{p['nz']} grid after 1 warm-up "
+                      f"step ({dt:.1f} s, FP64)")
+    # the same on one core (a shorter sample: one step takes seconds)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.time()
+        k = 0
+        while k < 1 or (time.time() - t0 < budget_s / 3 and k < 8):
+            s.step(1)
+            k += 1
+        dt1 = time.time() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    out["single_core"] = dict(value=nodes * k / dt1 / 1e6, unit="MLUPS", cores=1,
+                              sample=f"{k} coupled steps of the same grid ({dt1:.1f} s, FP64)")
+    return out
 
 
 PROFILE_STEPS = 20
@@ -273,6 +288,49 @@ def summarize_profiles(d: str):
     print("\n".join(lines))
 
 
+SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+               "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES"]
+
+
+def summarize_sq(d: str):
+    """Turn the csv of `rocprofv3 --pmc <SQ_COUNTERS> -- bench.py --profile-run` (under d/prof_sq) into
+    profiles/step_3d_flow_c3_sq.md: instruction counts per wavefront of the step kernels and the
+    share of the kernel time the VALU pipes are busy (wave64 binary32 VALU instructions issue over 4
+    cycles on a 16-lane SIMD; 1024 SIMDs at 2.4 GHz; kernel times from profiles/traffic.json)."""
+    import csv
+    import statistics as st
+    per = {}
+    with open(os.path.join(d, "prof_sq", "run_counter_collection.csv")) as fh:
+        for r in csv.DictReader(fh):
+            tag = _kernel_tag(r["Kernel_Name"])
+            if not tag.startswith("step_"):
+                continue
+            per.setdefault(tag, {}).setdefault(int(r["Dispatch_Id"]), {}).setdefault(r["Counter_Name"], 0.0)
+            per[tag][int(r["Dispatch_Id"])][r["Counter_Name"]] += float(r["Counter_Value"])
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+        times = {k: v["avg_us"] for k, v in json.load(fh).items()}
+    lines = ["# rocprofv3 SQ counters: fused coupled step, 3-D 192x128x128 with flow (C3)", "",
+             "Commands (from the repository root, TMPDIR=/tmp):", "",
+             "    rocprofv3 --pmc " + " ".join(SQ_COUNTERS) +
+             " -f csv -d gpurun_out/prof_sq -o run -- python3 bench.py --profile-run",
+             "    python3 bench.py --summarize-sq gpurun_out", "",
+             "Per wavefront (one wavefront = one 64-node row segment), mean over the dispatches:", "",
+             "| kernel | waves | VALU | SALU | VMEM read | VMEM write | LDS | VALU busy (4 cycles / instruction) |",
+             "|---|---|---|---|---|---|---|---|"]
+    for tag in sorted(per):
+        ds = list(per[tag].values())
+        m = {c: st.mean(x.get(c, 0.0) for x in ds) for c in SQ_COUNTERS}
+        w = m["SQ_WAVES"] or 1.0
+        busy = ""
+        if tag in times:
+            busy = f"{m['SQ_INSTS_VALU'] * 4 / (1024 * times[tag] * 1e-6 * 2.4e9):.0%}"
+        lines.append(f"| {tag} | {m['SQ_WAVES']:.0f} | {m['SQ_INSTS_VALU'] / w:.0f} | {m['SQ_INSTS_SALU'] / w:.0f} | "
+                     f"{m['SQ_INSTS_VMEM_RD'] / w:.1f} | {m['SQ_INSTS_VMEM_WR'] / w:.1f} | {m['SQ_INSTS_LDS'] / w:.1f} | {busy} |")
+    with open(os.path.join(ROOT, "profiles", "step_3d_flow_c3_sq.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,9 +346,13 @@ def main():
                     help="a short run of the headline kernel and a 1 GiB copy, for rocprofv3")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="summarise rocprofv3 csv output under DIR into profiles/")
+    ap.add_argument("--summarize-sq", metavar="DIR", help="summarise the SQ-counter run under DIR/prof_sq")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles)
+        return
+    if args.summarize_sq:
+        summarize_sq(args.summarize_sq)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this solver runs on a "

@@ -67,6 +67,8 @@ int orc_measure(const orc_params* P, const double* h, const double* g, const dou
 int orc_raymarch(const orc_params* P, const double* phi, int ndirs, const double* dirs, double* L_out);
 
 int orc_num_threads(void);
+/* Threads used by the following oracle calls (OpenMP); n <= 0 leaves the setting alone. */
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

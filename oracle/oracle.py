@@ -68,6 +68,8 @@ def lib():
         L.orc_measure.argtypes = [pp, dp, dp, dp, dp, ctypes.c_int, dp, dp, dp]
         L.orc_raymarch.argtypes = [pp, dp, ctypes.c_int, dp, dp]
         L.orc_num_threads.argtypes = []
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -115,6 +117,10 @@ def aniso(eps: float, p, grad_eps2: float = 1e-12):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int):
+    lib().orc_set_num_threads(int(n))
 
 
 class Sim:

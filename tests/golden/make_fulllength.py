@@ -1,0 +1,80 @@
+"""Write the oracle's state of the 3-D configurations after their full step counts, sampled, for
+the full-length parity test of the GPU path.
+
+    python tests/golden/make_fulllength.py c2     # 128^3 without flow, 5000 steps (minutes)
+    python tests/golden/make_fulllength.py c3     # 192x128x128 with flow, 20000 steps (hours)
+
+Only the oracle (binary64, OpenMP over the host's cores) and the seeded workload definitions are
+used. Stored per field (phi, U, and rho, ux, uy, uz with flow): the values on the planes z = nz/2
+and y = ny/2 through the seed centre (they cut the interface everywhere the crystal reaches) and at
+8192 nodes drawn with numpy's default_rng(2206), plus the maximum |value| over the whole grid (the
+denominator of the relative error). Also stored: the binary64 diagnostics (sum U, sum phi_prev,
+V_s, M') and the crystal extents along 16 directions in the x-y plane.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import oracle as O  # noqa: E402
+from paper_2206_02145_amd import workloads as W  # noqa: E402
+
+CASES = {"c2": (W.config2, 5000), "c3": (W.config3, 20000)}
+N_RANDOM = 8192
+
+
+def sample_nodes(p):
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    zc, yc = nz // 2, ny // 2
+    zz, yy, xx = np.meshgrid(np.array([zc]), np.arange(ny), np.arange(nx), indexing="ij")
+    a = np.stack([zz.ravel(), yy.ravel(), xx.ravel()], 1)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.array([yc]), np.arange(nx), indexing="ij")
+    b = np.stack([zz.ravel(), yy.ravel(), xx.ravel()], 1)
+    rng = np.random.default_rng(2206)
+    c = np.stack([rng.integers(0, nz, N_RANDOM), rng.integers(0, ny, N_RANDOM), rng.integers(0, nx, N_RANDOM)], 1)
+    return np.concatenate([a, b, c]).astype(np.int32)  # (z, y, x)
+
+
+def main(case):
+    cfg, steps = CASES[case]
+    p = cfg()
+    sim = O.Sim(p)
+    t0 = time.time()
+    chunk = 500
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        sim.step(n)
+        done += n
+        print(f"{case}: {done}/{steps} steps, {time.time() - t0:.0f} s", flush=True)
+    f = sim.fields()
+    nodes = sample_nodes(p)
+    z, y, x = nodes[:, 0], nodes[:, 1], nodes[:, 2]
+    names = ["phi", "U"] + (["rho", "ux", "uy", "uz"] if p["flow"] else [])
+    out = {"nodes": nodes}
+    for k in names:
+        out[k] = f[k][z, y, x]
+        out["absmax_" + k] = np.array(np.abs(f[k]).max())
+    dirs = W.directions(16)
+    L, mass = sim.measure(dirs)
+    out["L16"] = np.asarray(L)
+    for k, v in mass.items():
+        out["mass_" + k] = np.array(v)
+    meta = dict(case=case, steps=steps, params={k: (list(v) if isinstance(v, (tuple, list)) else v)
+                                                for k, v in p.items()},
+                oracle_threads=O.num_threads(), seconds=round(time.time() - t0, 1),
+                sample="planes z=nz/2 and y=ny/2, 8192 nodes from default_rng(2206)")
+    out["meta"] = np.array(json.dumps(meta))
+    path = os.path.join(HERE, f"fulllength_{case}.npz")
+    np.savez_compressed(path, **out)
+    print(f"wrote {path}: {os.path.getsize(path) / 1e6:.2f} MB", flush=True)
+
+
+if __name__ == "__main__":
+    for c in sys.argv[1:] or ["c2"]:
+        main(c)
