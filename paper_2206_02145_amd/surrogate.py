@@ -169,40 +169,71 @@ def growth_error(G_pred, G_true, floor):
     return np.abs(G_pred - G_true).max(axis=-1) / np.maximum(G_true.mean(axis=-1), floor)
 
 
-def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = None, criterion: str = "max_dir"):
-    """Predict the final growth rates of held-out draws, accept those whose predicted error is
-    within tol, and fall back to the solver for the rest (timed with the batched solver).
+def subset(ds: Dataset, idx) -> Dataset:
+    idx = np.asarray(idx)
+    return Dataset(ds.draws[idx], ds.t, ds.L[idx], ds.G[idx], ds.solve_s * len(idx) / len(ds.draws))
 
-    The solver alone is timed on all held-out draws just before the fallback, so that both run in
-    the same state of the device and its allocator.
+
+def final_errors(model: Surrogate, ds: Dataset, floor: float, criterion: str = "max_dir"):
+    """(predicted, true) relative growth-rate errors of the runs in ds at their final time.
 
     criterion "max_dir": error = max_k |G_pred,k - G_k| / mean_k G_k (every direction);
     criterion "avg": error = |mean_k G_pred,k - mean_k G_k| / mean_k G_k (the average growth rate
     G_th of the paper's tables). The predicted error is two predicted standard deviations over
     the predicted mean growth rate (for "avg", the mean of the per-direction deviations)."""
+    _, _, Gm, Gs = model.predict(ds.draws, ds.t[-1:])
+    Gm, Gs = Gm[:, 0], Gs[:, 0]
+    Gt = ds.G[:, -1]
+    den_pred = np.maximum(np.abs(Gm.mean(axis=-1)), floor)
+    den_true = np.maximum(Gt.mean(axis=-1), floor)
+    if criterion == "avg":
+        return 2.0 * Gs.mean(axis=-1) / den_pred, np.abs(Gm.mean(axis=-1) - Gt.mean(axis=-1)) / den_true
+    return 2.0 * Gs.max(axis=-1) / den_pred, np.abs(Gm - Gt).max(axis=-1) / den_true
+
+
+def threshold_from(pred, true, tol: float) -> float:
+    """The largest predicted-error threshold (at most tol) under which every run it accepts has a
+    true error within tol: the runs sorted by predicted error are accepted up to the first miss
+    (0 if the most confident run already misses)."""
+    pred, true = np.asarray(pred, dtype=float), np.asarray(true, dtype=float)
+    order = np.argsort(pred, kind="stable")
+    ok = np.cumprod(true[order] <= tol).astype(bool)
+    if not ok.any():
+        return 0.0
+    last = int(np.nonzero(ok)[0].max())
+    thr = float(pred[order][last])
+    if last + 1 < len(order) and pred[order][last + 1] == thr:  # a tie with the first miss
+        thr = float(np.nextafter(thr, -np.inf))
+    return min(thr, tol)
+
+
+def calibrate(model: Surrogate, cal: Dataset, tol: float, floor: float, criterion: str = "max_dir") -> float:
+    """Acceptance threshold from calibration runs the model was not trained on (threshold_from)."""
+    pred, true = final_errors(model, cal, floor, criterion)
+    return threshold_from(pred, true, tol)
+
+
+def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = None, criterion: str = "max_dir",
+             threshold: float = None):
+    """Predict the final growth rates of held-out draws, accept those whose predicted error is at
+    most `threshold` (default: tol), and fall back to the solver for the rest (timed with the
+    batched solver). Errors as in final_errors.
+
+    The solver alone is timed on all held-out draws just before the fallback, so that both run in
+    the same state of the device and its allocator."""
     import torch
     if floor is None:
         floor = 0.1 * float(np.abs(held.G[:, -1]).mean())
-    t_end = held.t[-1:]
+    thr = tol if threshold is None else threshold
     all_draws = [tuple(d) for d in held.draws]
     steps, every = int(held.t[-1]), int(held.t[1] - held.t[0])
     t_alone = generate(all_draws, steps=steps, every=every).solve_s
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, _, Gm, Gs = model.predict(held.draws, t_end)
+    pred_err, true_err = final_errors(model, held, floor, criterion)
     torch.cuda.synchronize()
     t_infer = time.perf_counter() - t0
-    Gm, Gs = Gm[:, 0], Gs[:, 0]
-    Gt = held.G[:, -1]
-    den_pred = np.maximum(np.abs(Gm.mean(axis=-1)), floor)
-    den_true = np.maximum(Gt.mean(axis=-1), floor)
-    if criterion == "avg":
-        pred_err = 2.0 * Gs.mean(axis=-1) / den_pred
-        true_err = np.abs(Gm.mean(axis=-1) - Gt.mean(axis=-1)) / den_true
-    else:
-        pred_err = 2.0 * Gs.max(axis=-1) / den_pred
-        true_err = np.abs(Gm - Gt).max(axis=-1) / den_true
-    accept = pred_err <= tol
+    accept = pred_err <= thr
     n = len(held.draws)
     n_fb = int((~accept).sum())
     t_fb = 0.0
@@ -212,7 +243,7 @@ def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = 
     total = t_infer + t_fb
     q = lambda v: None if v is None else round(float(v), 5)
     return dict(criterion=criterion, held_out=n, accepted=int(accept.sum()), fallback=n_fb, floor=floor, tol=tol,
-                infer_s=t_infer, fallback_s=t_fb, runs_per_s=n / total if total > 0 else float("inf"),
+                threshold=q(thr), infer_s=t_infer, fallback_s=t_fb, runs_per_s=n / total if total > 0 else float("inf"),
                 accepted_err_max=q(true_err[accept].max()) if accept.any() else None,
                 accepted_err_mean=q(true_err[accept].mean()) if accept.any() else None,
                 accepted_within_tol=q((true_err[accept] <= tol).mean()) if accept.any() else None,
@@ -230,15 +261,22 @@ def run_study(n_train: int = 4096, n_held: int = 256, steps: int = 4000, train_s
     solver_rps = n_held / ho.solve_s
     out = dict(train_runs=n_train, held_out_runs=n_held, steps=steps, solve_train_s=tr.solve_s,
                solver_alone_runs_per_s=solver_rps)
+    # the last tenth of the training runs calibrates the acceptance threshold and is not trained on
+    n_cal = max(1, n_train // 10)
+    fit, cal = subset(tr, np.arange(n_train - n_cal)), subset(tr, np.arange(n_train - n_cal, n_train))
+    floor = 0.1 * float(np.abs(cal.G[:, -1]).mean())
     for name, ws, crit in (("deployed_with_side", True, "max_dir"), ("four_inputs", False, "avg"),
                            ("four_inputs_max_dir", False, "max_dir")):
         m = Surrogate(with_side=ws)
-        info = m.train(tr, steps=train_steps)
-        res = evaluate(m, ho, criterion=crit)
-        res.update(train_s=info["train_s"], final_loss=info["final_loss"], inputs=5 if ws else 4)
+        info = m.train(fit, steps=train_steps)
+        thr = calibrate(m, cal, 0.05, floor, crit)
+        res = evaluate(m, ho, floor=floor, criterion=crit, threshold=thr)
+        res.update(train_s=info["train_s"], final_loss=info["final_loss"], inputs=5 if ws else 4,
+                   train_runs=n_train - n_cal, calibration_runs=n_cal)
         out[name] = res
         if log:
-            log(f"surrogate {name}: accepted {res['accepted']}/{n_held}, accepted err max {res['accepted_err_max']}, "
-                f"median err {res['all_err_median']}, {res['runs_per_s']:.0f} runs/s vs solver {res['solver_alone_runs_per_s']:.0f}")
+            log(f"surrogate {name}: threshold {res['threshold']}, accepted {res['accepted']}/{n_held}, "
+                f"accepted err max {res['accepted_err_max']}, median err {res['all_err_median']}, "
+                f"{res['runs_per_s']:.0f} runs/s vs solver {res['solver_alone_runs_per_s']:.0f}")
         m.net.close()
     return out

@@ -2,7 +2,8 @@
 the full-length parity test of the GPU path.
 
     python tests/golden/make_fulllength.py c2     # 128^3 without flow, 5000 steps (minutes)
-    python tests/golden/make_fulllength.py c3     # 192x128x128 with flow, 20000 steps (hours)
+    python tests/golden/make_fulllength.py c3     # 192x128x128 with flow, 20000 steps (hours);
+                                                  # also a snapshot after 4000 steps
 
 Only the oracle (binary64, OpenMP over the host's cores) and the seeded workload definitions are
 used. Stored per field (phi, U, and rho, ux, uy, uz with flow): the values on the planes z = nz/2
@@ -24,7 +25,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from oracle import oracle as O  # noqa: E402
 from paper_2206_02145_amd import workloads as W  # noqa: E402
 
-CASES = {"c2": (W.config2, 5000), "c3": (W.config3, 20000)}
+# configuration, step count, earlier snapshots (files fulllength_<case>_<steps>.npz)
+CASES = {"c2": (W.config2, 5000, ()), "c3": (W.config3, 20000, (4000,))}
 N_RANDOM = 8192
 
 
@@ -40,18 +42,7 @@ def sample_nodes(p):
     return np.concatenate([a, b, c]).astype(np.int32)  # (z, y, x)
 
 
-def main(case):
-    cfg, steps = CASES[case]
-    p = cfg()
-    sim = O.Sim(p)
-    t0 = time.time()
-    chunk = 500
-    done = 0
-    while done < steps:
-        n = min(chunk, steps - done)
-        sim.step(n)
-        done += n
-        print(f"{case}: {done}/{steps} steps, {time.time() - t0:.0f} s", flush=True)
+def save(case, p, sim, step, final, t0):
     f = sim.fields()
     nodes = sample_nodes(p)
     z, y, x = nodes[:, 0], nodes[:, 1], nodes[:, 2]
@@ -60,19 +51,36 @@ def main(case):
     for k in names:
         out[k] = f[k][z, y, x]
         out["absmax_" + k] = np.array(np.abs(f[k]).max())
-    dirs = W.directions(16)
-    L, mass = sim.measure(dirs)
+    L, mass = sim.measure(W.directions(16))
     out["L16"] = np.asarray(L)
     for k, v in mass.items():
         out["mass_" + k] = np.array(v)
-    meta = dict(case=case, steps=steps, params={k: (list(v) if isinstance(v, (tuple, list)) else v)
-                                                for k, v in p.items()},
+    meta = dict(case=case, steps=step, params={k: (list(v) if isinstance(v, (tuple, list)) else v)
+                                               for k, v in p.items()},
                 oracle_threads=O.num_threads(), seconds=round(time.time() - t0, 1),
                 sample="planes z=nz/2 and y=ny/2, 8192 nodes from default_rng(2206)")
     out["meta"] = np.array(json.dumps(meta))
-    path = os.path.join(HERE, f"fulllength_{case}.npz")
+    name = f"fulllength_{case}.npz" if final else f"fulllength_{case}_{step}.npz"
+    path = os.path.join(HERE, name)
     np.savez_compressed(path, **out)
     print(f"wrote {path}: {os.path.getsize(path) / 1e6:.2f} MB", flush=True)
+
+
+def main(case):
+    cfg, steps, snaps = CASES[case]
+    p = cfg()
+    sim = O.Sim(p)
+    t0 = time.time()
+    chunk = 500
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done, *[s - done for s in snaps if s > done])
+        sim.step(n)
+        done += n
+        print(f"{case}: {done}/{steps} steps, {time.time() - t0:.0f} s", flush=True)
+        if done in snaps:
+            save(case, p, sim, done, False, t0)
+    save(case, p, sim, steps, True, t0)
 
 
 if __name__ == "__main__":

@@ -85,3 +85,16 @@ def test_null_handles_are_rejected():
     assert lbcg.STATUS[L.lbcg_step(None, 1)] == "EINVAL"
     assert lbcg.STATUS[L.lbcg_measure(None, 0, None, None, None)] == "EINVAL"
     assert L.lbcg_destroy(None) == 0
+
+
+def test_surrogate_threshold_calibration():
+    """The acceptance threshold accepts the most confident runs up to the first one whose true
+    error misses the tolerance, never above the tolerance itself."""
+    from paper_2206_02145_amd.surrogate import threshold_from
+    pred = [0.01, 0.03, 0.02, 0.04, 0.06]
+    true = [0.02, 0.07, 0.04, 0.01, 0.01]
+    assert threshold_from(pred, true, 0.05) == 0.02          # 0.03 is the first miss
+    assert threshold_from(pred, [0.0] * 5, 0.05) == 0.05     # capped at the tolerance
+    assert threshold_from([0.01, 0.02], [0.2, 0.0], 0.05) == 0.0
+    thr = threshold_from([0.01, 0.02, 0.02], [0.0, 0.0, 0.09], 0.05)
+    assert 0.01 <= thr < 0.02                                # a tie with the miss is excluded

@@ -1,8 +1,17 @@
 """Parity at full size and full length: the HIP path against the oracle's state of the 3-D
-configurations after their own step counts (128^3 without flow, 5000 steps; 192x128x128 with flow,
-20000 steps), on the sampled outputs that tests/golden/make_fulllength.py stored (two planes through
-the seed centre and 8192 random nodes). The bar is the binary32 one: max |error| over the samples
-divided by max |value| over the whole grid, 1e-4 per field."""
+configurations (128^3 without flow after its 5000 steps; 192x128x128 with flow after 4000 and after
+its 20000 steps), on the sampled outputs that tests/golden/make_fulllength.py stored (two planes
+through the seed centre and 8192 random nodes).
+
+Pointwise bar (binary32): max |error| over the samples divided by max |value| over the whole grid,
+1e-4 per field. The 192x128x128 case is checked pointwise at 4000 steps only: with eps = 0.05
+(above 1/35, so the interface stiffness 1 - 35 eps cos 6 theta is negative near the axes) the
+interface shape amplifies any perturbation, rounding included, by about 20x per 2000 steps
+from step 4000 on, so two correct runs that round differently part pointwise (binary32 against
+binary64 on the GPU: phi 1.4e-5 at 4000 steps, 1e-2 at 8000, 0.24 at 20000). After 20000 steps
+the test checks what that amplification leaves alone: the solid volume, the crystal extents and
+the binary64 diagnostics; the pointwise errors are printed. The binary16 flow-storage mode is
+reported per field with a loose bound."""
 import json
 import os
 
@@ -27,8 +36,9 @@ def lb():
     return lbcg
 
 
-def load(case):
-    path = os.path.join(GOLDEN, f"fulllength_{case}.npz")
+def load(case, step=None):
+    name = f"fulllength_{case}.npz" if step is None else f"fulllength_{case}_{step}.npz"
+    path = os.path.join(GOLDEN, name)
     if not os.path.exists(path):
         pytest.skip(f"{path} not generated (python tests/golden/make_fulllength.py {case})")
     z = np.load(path, allow_pickle=False)
@@ -50,30 +60,58 @@ def run(lb, p, prec, steps):
     return s
 
 
-@pytest.mark.parametrize("case", ["c2", "c3"])
-def test_full_length_fp32(lb, case):
-    z, meta, p = load(case)
-    steps = meta["steps"]
-    print(f"[fulllength] {case} fp32 {p['nx']}x{p['ny']}x{p['nz']} flow={p['flow']} steps={steps}", flush=True)
-    s = run(lb, p, "fp32", steps)
+def errors(s, z, p):
     nz_, ny_, nx_ = z["nodes"][:, 0], z["nodes"][:, 1], z["nodes"][:, 2]
-    names = ["phi", "U"] + (["rho", "ux", "uy", "uz"] if p["flow"] else [])
     errs = {}
-    for k in names:
-        got = s.read(k)[nz_, ny_, nx_]
-        errs[k] = float(np.abs(got - z[k]).max() / z["absmax_" + k])
+    for k in ("phi", "U") + (("rho",) if p["flow"] else ()):
+        errs[k] = float(np.abs(s.read(k)[nz_, ny_, nx_] - z[k]).max() / z["absmax_" + k])
     if p["flow"]:  # the velocity as a vector, over the largest component
         um = max(float(z["absmax_" + c]) for c in ("ux", "uy", "uz"))
         errs["u"] = max(float(np.abs(s.read(c)[nz_, ny_, nx_] - z[c]).max()) for c in ("ux", "uy", "uz")) / um
-        for c in ("ux", "uy", "uz"):
-            errs.pop(c)
+    return errs
+
+
+def aggregates(s, z):
     L, mass = s.measure(W.directions(16))
     dL = float(np.abs(L - z["L16"]).max())
+    dVs = abs(mass["Vs"] - float(z["mass_Vs"])) / abs(float(z["mass_Vs"]))
     dM = abs(mass["Mprime"] - float(z["mass_Mprime"])) / abs(float(z["mass_Mprime"]))
-    print(f"[fulllength] {case} fp32 errors: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
-          f"; max |dL| {dL:.2e} cells; M' rel diff {dM:.2e}", flush=True)
+    return dL, dVs, dM
+
+
+@pytest.mark.parametrize("case,step", [("c2", None), ("c3", 4000)])
+def test_full_size_pointwise_fp32(lb, case, step):
+    z, meta, p = load(case, step)
+    steps = meta["steps"]
+    print(f"[fulllength] {case} fp32 {p['nx']}x{p['ny']}x{p['nz']} flow={p['flow']} steps={steps}", flush=True)
+    s = run(lb, p, "fp32", steps)
+    errs = errors(s, z, p)
+    dL, dVs, dM = aggregates(s, z)
+    print(f"[fulllength] {case} fp32 @{steps}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
+          f"; max |dL| {dL:.2e} cells; Vs {dVs:.2e}; M' {dM:.2e}", flush=True)
     for k, v in errs.items():
         assert v <= 1e-4, (case, k, v)
-    assert dL <= 0.05
-    assert dM <= (1e-6 if not p["flow"] else 1e-4)
+    assert dL <= 0.05 and dVs <= 1e-5
+    assert dM <= (1e-6 if not p["flow"] else 1e-5)
+    s.close()
+    if p["flow"]:
+        s = run(lb, p, "fp16shift", steps)
+        e16 = errors(s, z, p)
+        print(f"[fulllength] {case} fp16shift @{steps}: " + ", ".join(f"{k}={v:.2e}" for k, v in e16.items()),
+              flush=True)
+        for k, v in e16.items():
+            assert v <= 5e-2, (case, "fp16shift", k, v)
+        s.close()
+
+
+def test_full_length_flow_aggregates_fp32(lb):
+    z, meta, p = load("c3")
+    steps = meta["steps"]
+    s = run(lb, p, "fp32", steps)
+    errs = errors(s, z, p)
+    dL, dVs, dM = aggregates(s, z)
+    print(f"[fulllength] c3 fp32 @{steps} pointwise (amplified, not asserted): " +
+          ", ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
+          f"; aggregates: max |dL| {dL:.3f} cells, Vs {dVs:.2e}, M' {dM:.2e}", flush=True)
+    assert dL <= 1.0 and dVs <= 2e-3 and dM <= 1e-3
     s.close()
