@@ -291,9 +291,12 @@ static void moments(const orc_params* P, const double* h, const double* g, const
     }
 }
 
+static int is_wall(const orc_params* P, long i) { return P->wall && P->wall[i]; }
+
 /* phi at the node x + c (periodic wrap in y, z, and in x when periodic; at an open x face the
- * ghost takes the value of the face node, R23). */
-static double phi_at(const orc_params* P, const double* phi, int x, int y, int z) {
+ * ghost takes the value of the face node, R23; a wall neighbour takes the value of the node
+ * itself, own, so that the normal derivative vanishes at the wall, R28). */
+static double phi_at(const orc_params* P, const double* phi, int x, int y, int z, long own) {
     if (P->xbc == 0) {
         x = wrap(x, P->nx);
     } else {
@@ -302,7 +305,8 @@ static double phi_at(const orc_params* P, const double* phi, int x, int y, int z
     }
     y = wrap(y, P->ny);
     z = wrap(z, P->nz);
-    return phi[node(P, x, y, z)];
+    long j = node(P, x, y, z);
+    return is_wall(P, j) ? phi[own] : phi[j];
 }
 
 /* Phase 2: grad phi = (1/cs2) sum_b w_b c_b phi(x + c_b) over the D2Q9 / D3Q19 stencil (R5). */
@@ -312,12 +316,12 @@ static void gradient(const orc_params* P, scratch* s) {
     for (long r = 0; r < (long)P->nz * P->ny; r++) {
         int z = (int)(r / P->ny), y = (int)(r % P->ny);
         for (int x = 0; x < P->nx; x++) {
+            long i = node(P, x, y, z);
             double p[3] = {0.0, 0.0, 0.0};
             for (int b = 0; b < G.q; b++) {
-                double phib = phi_at(P, s->phi, x + G.c[b][0], y + G.c[b][1], z + G.c[b][2]);
+                double phib = phi_at(P, s->phi, x + G.c[b][0], y + G.c[b][1], z + G.c[b][2], i);
                 for (int d = 0; d < 3; d++) p[d] += G.w[b] * G.c[b][d] * phib;
             }
-            long i = node(P, x, y, z);
             s->px[i] = p[0] / G.cs2;
             s->py[i] = p[1] / G.cs2;
             s->pz[i] = p[2] / G.cs2;
@@ -326,7 +330,7 @@ static void gradient(const orc_params* P, scratch* s) {
 }
 
 /* Where population a leaving node (x,y,z) lands: 0 inside (index in *dst), 1 through the inlet
- * face (x < 0), 2 through the outlet face (x >= nx). */
+ * face (x < 0), 2 through the outlet face (x >= nx), 3 onto a wall node. */
 static int destination(const orc_params* P, const lattice* L, int a, int x, int y, int z, long* dst) {
     int xd = x + L->c[a][0];
     int yd = wrap(y + L->c[a][1], P->ny);
@@ -338,7 +342,7 @@ static int destination(const orc_params* P, const lattice* L, int a, int x, int 
         if (xd >= P->nx) return 2;
     }
     *dst = node(P, xd, yd, zd);
-    return 0;
+    return is_wall(P, *dst) ? 3 : 0;
 }
 
 /* Phase 3: collide at every node with time-n data only, then stream (push) into the new arrays. */
@@ -355,6 +359,7 @@ static void collide_stream(const orc_params* P, const double* h, const double* g
         int z = (int)(r / P->ny), y = (int)(r % P->ny);
         for (int x = 0; x < P->nx; x++) {
             long i = node(P, x, y, z);
+            if (is_wall(P, i)) continue; /* walls are frozen (R28) */
             double phi = s->phi[i], U = s->U[i];
             double p[3] = {s->px[i], s->py[i], s->pz[i]};
             double as, Nv[3];
@@ -373,7 +378,8 @@ static void collide_stream(const orc_params* P, const double* h, const double* g
                 int where = destination(P, &S, a, x, y, z, &d);
                 if (where == 0) {
                     s->hn[a * N + d] = (hstar - (1.0 - a2) * h[a * N + d]) / a2;
-                } else if (where == 1) { /* zero-flux bounce-back at the inlet face (R15, R27) */
+                } else if (where == 1 || where == 3) { /* zero-flux bounce-back: inlet face (R15, R27)
+                                                          * or wall (R28) */
                     int b = opposite(&S, a);
                     s->hn[b * N + i] = (hstar - (1.0 - a2) * h[b * N + i]) / a2;
                 }
@@ -398,6 +404,8 @@ static void collide_stream(const orc_params* P, const double* h, const double* g
                         int b = opposite(&V, a);
                         double cuw = V.c[a][0] * uw[0] + V.c[a][1] * uw[1] + V.c[a][2] * uw[2];
                         s->fn[b * N + i] = fstar - 2.0 * V.w[a] * 1.0 * cuw / V.cs2;
+                    } else if (where == 3) { /* no-slip halfway bounce-back at a wall at rest (R28) */
+                        s->fn[opposite(&V, a) * N + i] = fstar;
                     }
                 }
             }
@@ -420,6 +428,8 @@ static void collide_stream(const orc_params* P, const double* h, const double* g
                 } else if (where == 1) { /* anti-bounce-back, Dirichlet U = U_in (R15) */
                     int b = opposite(&S, a);
                     s->gn[b * N + i] = -gstar + 2.0 * S.w[a] * P->U_in;
+                } else if (where == 3) { /* zero-flux bounce-back at a wall (R28) */
+                    s->gn[opposite(&S, a) * N + i] = gstar;
                 }
             }
         }
@@ -431,10 +441,12 @@ static void collide_stream(const orc_params* P, const double* h, const double* g
 static void outlet_fill(const orc_params* P, const lattice* L, double* pn) {
     long N = nnodes(P);
     for (int z = 0; z < P->nz; z++)
-        for (int y = 0; y < P->ny; y++)
+        for (int y = 0; y < P->ny; y++) {
+            if (is_wall(P, node(P, P->nx - 1, y, z))) continue; /* walls stay frozen (R28) */
             for (int a = 0; a < L->q; a++)
                 if (L->c[a][0] < 0)
                     pn[a * N + node(P, P->nx - 1, y, z)] = pn[a * N + node(P, P->nx - 2, y, z)];
+        }
 }
 
 int orc_step(const orc_params* P, double* h, double* g, double* f, double* phi_prev, int64_t nsteps) {
@@ -460,6 +472,11 @@ int orc_step(const orc_params* P, double* h, double* g, double* f, double* phi_p
     s.fn = P->flow ? s.gn + (long)S.q * N : NULL;
 
     for (int64_t n = 0; n < nsteps; n++) {
+        if (P->wall) { /* wall nodes are never written: they keep their values */
+            memcpy(s.hn, h, sizeof(double) * S.q * N);
+            memcpy(s.gn, g, sizeof(double) * S.q * N);
+            if (P->flow) memcpy(s.fn, f, sizeof(double) * V.q * N);
+        }
         moments(P, h, g, f, &s);
         gradient(P, &s);
         collide_stream(P, h, g, f, phi_prev, &s);
@@ -590,6 +607,7 @@ int orc_measure(const orc_params* P, const double* h, const double* g, const dou
     if (mass_out) {
         double sU = 0.0, sP = 0.0, Vs = 0.0, Mp = 0.0, umax = 0.0, bad = 0.0;
         for (long i = 0; i < N; i++) {
+            if (is_wall(P, i)) continue; /* diagnostics cover the fluid and the crystal (R28) */
             sU += U[i];
             sP += phi_prev[i];
             Vs += 0.5 * (1.0 + phi[i]);

@@ -30,6 +30,8 @@ typedef struct {
     double nu, h_drag, u_in, U0, U_in; /* viscosity, drag constant, inlet velocity, initial / inlet U */
     double seed_c[3], seed_R;          /* seed centre (node coordinates) and radius */
     double grad_eps2;                  /* |grad phi|^2 threshold below which a_s = 1, N = 0 */
+    const uint8_t* wall;               /* NULL, or one flag per node (1 = solid wall node, R28):
+                                        * walls are frozen, populations aimed at them bounce back */
 } orc_params;
 
 /* Lattice tables. kind: 0 = D2Q5, 1 = D3Q7, 2 = D2Q9, 3 = D3Q19.
@@ -56,7 +58,7 @@ int orc_step(const orc_params* P, double* h, double* g, double* f, double* phi_p
 int orc_fields(const orc_params* P, const double* h, const double* g, const double* f, double* phi,
                double* U, double* rho, double* ux, double* uy, double* uz);
 
-/* Diagnostics. mass_out[6] = {sum U, sum phi_prev, V_s = sum (1+phi)/2,
+/* Diagnostics (sums over the non-wall nodes). mass_out[6] = {sum U, sum phi_prev, V_s = sum (1+phi)/2,
  * M' = sum U + sum (1 + phi_prev), max |u*|, number of non-finite phi/U/rho values}.
  * L_out[ndirs] = crystal extent along each unit direction dirs[3k..3k+2] from the seed centre.
  * Either output may be NULL. */

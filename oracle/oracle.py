@@ -33,6 +33,7 @@ class OrcParams(ctypes.Structure):
         ("U0", ctypes.c_double), ("U_in", ctypes.c_double),
         ("seed_c", ctypes.c_double * 3), ("seed_R", ctypes.c_double),
         ("grad_eps2", ctypes.c_double),
+        ("wall", ctypes.c_void_p),
     ]
 
 
@@ -142,6 +143,15 @@ class Sim:
                                 _dp(self.phi_prev))
             if rc != 0:
                 raise ValueError("oracle rejected the parameters")
+
+    def set_walls(self, mask):
+        """Solid wall nodes (nonzero entries of a (nz, ny, nx) mask), or None for none."""
+        if mask is None:
+            self.wall = None
+            self.cp.wall = None
+            return
+        self.wall = np.ascontiguousarray(np.broadcast_to(mask, self.shape), dtype=np.uint8)
+        self.cp.wall = self.wall.ctypes.data
 
     def set_flow_equilibrium(self, rho, ux, uy, uz=None):
         arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), self.shape))

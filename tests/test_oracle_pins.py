@@ -593,3 +593,54 @@ def test_self_convergence_second_order(orc):
         e2 = np.abs(b[k] - c[k]).max()
         assert 3.3 < e1 / e2 < 4.7, (k, e1, e2)  # order log2(e1/e2) in (1.7, 2.2)
 
+
+# --------------------------------------------------------------------------------------------
+# Solid walls (reactor walls and baffles, Section 4: zero flux for phase field and solute; no-slip
+# for the flow; reading R28)
+# --------------------------------------------------------------------------------------------
+
+def test_channel_between_walls_develops_poiseuille(orc):
+    """Inflow through a channel between two wall rows: downstream the profile is the Poiseuille
+    parabola u(y) = 6 ubar y (H - y) / H^2 with the halfway walls at y = 0.5 and ny - 1.5. (The
+    zero-gradient outlet fixes no pressure level, so with wall friction the density keeps rising
+    slowly and the flow has no steady state; the profile's shape is settled all the same.)"""
+    ny, nx = 22, 128
+    p = W.params(dim=2, nx=nx, ny=ny, flow=1, xbc=1, u_in=0.02, U0=0.1, U_in=0.1, seed_R=-1e9)
+    s = orc.Sim(p)
+    m = np.zeros((1, ny, nx), np.uint8)
+    m[0, 0, :] = m[0, ny - 1, :] = 1
+    s.set_walls(m)
+    s.set_flow_equilibrium(1.0, 0.0, 0.0)
+    s.step(6000)
+    f = s.fields()
+    H = ny - 2
+    y = np.arange(1, ny - 1) - 0.5
+    ux = f["ux"][0, 1:ny - 1, 90]
+    par = 6 * ux.mean() * y * (H - y) / H ** 2
+    assert np.abs(ux - par).max() < 5e-3 * ux.max()
+    uy = f["uy"][0, 1:ny - 1, 90]
+    assert np.abs(uy + uy[::-1]).max() < 1e-15 and np.abs(uy).max() < 1e-2 * ux.max()  # mirror symmetry
+
+
+def test_walls_conserve_solute_and_mass(orc):
+    """A box closed by wall rows (zero flux for U, no-slip for f): the solute-plus-solid invariant
+    and the fluid mass stay exact while a seed grows and a shear flow decays against the walls."""
+    n = 48
+    p = W.params(dim=2, nx=n, ny=n, flow=1, xbc=0, U0=0.2, U_in=0.2, seed_c=(24, 24, 0), seed_R=6.0)
+    s = orc.Sim(p)
+    m = np.zeros((1, n, n), np.uint8)
+    m[0, 0, :] = 1      # with the periodic wrap: walls below and above the fluid rows 1 .. n-1
+    m[0, :, 0] = 1      # and left / right of the columns 1 .. n-1
+    s.set_walls(m)
+    yy = np.arange(n)[None, :, None] * np.ones((1, 1, n))
+    s.set_flow_equilibrium(1.0, 0.01 * np.sin(2 * np.pi * yy / n), 0.0)
+    fl = ~m.astype(bool)
+    M0 = s.measure()[1]["Mprime"]
+    rho0 = s.fields()["rho"][fl].sum()
+    s.step(400)
+    M1 = s.measure()[1]["Mprime"]
+    f = s.fields()
+    assert abs(M1 - M0) < 1e-12 * abs(M0)
+    assert abs(f["rho"][fl].sum() - rho0) < 1e-12 * rho0
+    assert f["phi"].max() > 0.9  # the seed is still there and growing
+
