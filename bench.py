@@ -87,13 +87,15 @@ def time_steps(s, steps: int, measure_every: int = 0, dirs=None):
     return e0.elapsed_time(e1)
 
 
-def gpu_case(name, p, prec, steps, warmup, with_measure):
+def gpu_case(name, p, prec, steps, warmup, with_measure, walls=None):
     import torch
 
     from paper_2206_02145_amd import lbcg
     from paper_2206_02145_amd import workloads as W
     nodes = p["nx"] * p["ny"] * p["nz"]
     s = lbcg.Solver(p, prec)
+    if walls is not None:
+        s.set_walls(walls)
     variant = s.variants()[s.variant]  # the default tiling (the fastest measured on MI355X)
     dirs = W.directions(16, p["dim"])
     s.step(warmup)
@@ -384,6 +386,8 @@ def main():
     head = gpu_case("3-D flow 192x128x128 fp32", p3, "fp32", args.steps, args.warmup, True)
     f16 = gpu_case("3-D flow 192x128x128 fp16shift", p3, "fp16shift", args.steps, args.warmup, False)
     c2 = gpu_case("3-D no-flow 128^3 fp32", W.config2(), "fp32", args.steps, args.warmup, False)
+    pw, mw = W.config3_walls()
+    c3w = gpu_case("3-D flow 192x128x128 fp32, walls and a baffle", pw, "fp32", args.steps, args.warmup, False, mw)
     sweep = None if args.no_sweep else sweep_case(args.sweep_n, args.sweep_steps, MEASURE_EVERY)
     surr = None
     if not args.no_surrogate:
@@ -424,6 +428,7 @@ def main():
         "variants": {
             "fp16shift_flow": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in f16.items()},
             "no_flow_128cube": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c2.items()},
+            "flow_walls_baffle": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c3w.items()},
         },
     }
     print(json.dumps(rec), flush=True)

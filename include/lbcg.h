@@ -79,7 +79,7 @@ typedef struct {
     int32_t flow;        /* 1: flow lattice on; 0: u* = 0 everywhere */
     int32_t precision;   /* lbcg_precision */
     int32_t xbc;         /* lbcg_xbc: periodic, or inlet at x = 0 / outlet at x = nx-1 */
-    int32_t reserved;    /* must be 0 */
+    int32_t walls;       /* 0: none; 1: the workspace keeps a solid-wall mask (lbcg_set_walls) */
     double W0, tau0;     /* interface width and time (Eq. a); tau0 > 0, W0 > 0 */
     double lambda;       /* coupling constant of Eq. (a) */
     double D;            /* solute diffusivity (Eq. b); >= 0 */
@@ -184,6 +184,21 @@ lbcg_status lbcg_state_save(lbcg_handle* h, void* dst, size_t dst_bytes, int dst
  * this solver; ENOMEM if src_bytes is short. Clears the non-finite flag; the crystal-size history
  * of lbcg_measure is kept. Synchronises. */
 lbcg_status lbcg_state_load(lbcg_handle* h, const void* src, size_t src_bytes, int src_on_device);
+
+/* ---- Solid walls (reactor walls and baffles, Section 4: zero-flux phase field and solute, no-slip
+ * flow) ----
+ * For a solver created with walls = 1: set the wall mask, one byte per node in the plain layout
+ * [z][y][x], nonzero = solid wall node (the mask starts empty). Wall nodes are frozen: they are
+ * not updated and push nothing. A population a fluid node would push onto a wall node is bounced
+ * back into the node's opposite population instead (halfway bounce-back): f with the wall at rest
+ * (no-slip), g unchanged (zero solute flux), h by Eq. (d) with the old value of the slot it is
+ * written to (zero phase-field flux, as at the inlet). In the phi gradient a wall neighbour takes
+ * the node's own value (zero normal derivative). lbcg_measure's sums skip wall nodes; fields read
+ * at wall nodes show their frozen state. With open x faces the outlet copy pairs the last two
+ * columns of each row, so there they must be both wall or both fluid. EINVAL: walls = 0 at
+ * creation, a mask that is too small, or a row that breaks the outlet pairing. Synchronises.
+ * Batches do not take walls. */
+lbcg_status lbcg_set_walls(lbcg_handle* h, const uint8_t* mask, size_t bytes, int mask_on_device);
 
 /* Release the host handle (the workspace stays the caller's). NULL is accepted. */
 lbcg_status lbcg_destroy(lbcg_handle* h);

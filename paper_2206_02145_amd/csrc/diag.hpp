@@ -162,6 +162,7 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_kernel(InstDev I, int par,
     double acc[RED_VALUES] = {0, 0, 0, 0, 0, 0};
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
          i += (long long)gridDim.x * blockDim.x) {
+        if (I.wall && I.wall[i]) continue;  // the sums cover the fluid and the crystal
         real psi, Ut, rho, ux, uy, uz;
         node_moments<DIM, FLOW, real, fst>(I, par, i, psi, Ut, rho, ux, uy, uz);
         const double U = (double)Ut + I.U0;

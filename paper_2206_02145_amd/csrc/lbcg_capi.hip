@@ -76,7 +76,7 @@ void validate(const lbcg_params* p) {
         throw Error(LBCG_EINVAL, "the binary16 shifted storage applies to the flow populations (flow = 1)");
     if (p->xbc != LBCG_PERIODIC && p->xbc != LBCG_INFLOW_OUTFLOW) throw Error(LBCG_EINVAL, "unknown xbc");
     if (p->xbc == LBCG_INFLOW_OUTFLOW && p->nx < 3) throw Error(LBCG_EINVAL, "open x faces need nx >= 3");
-    if (p->reserved != 0) throw Error(LBCG_EINVAL, "reserved must be 0");
+    if (p->walls != 0 && p->walls != 1) throw Error(LBCG_EINVAL, "walls must be 0 or 1");
     const double N = (double)p->nx * p->ny * p->nz;
     if (N >= 536870912.0)  // each population plane is addressed with 32-bit byte offsets
         throw Error(LBCG_EINVAL, "grid too large (at most 2^29 - 1 nodes)");
@@ -95,7 +95,7 @@ void validate(const lbcg_params* p) {
 }
 
 struct Layout {
-    size_t h[2], g[2], f[2], phi_prev, staging, partials, dirs, out, total;
+    size_t h[2], g[2], f[2], phi_prev, staging, partials, dirs, out, wall, total;  // wall: 0 = none
 };
 
 Layout layout_of(const lbcg_params* p) {
@@ -116,6 +116,7 @@ Layout layout_of(const lbcg_params* p) {
     L.partials = take((RED_BLOCKS + 1) * RED_VALUES * 8);  // block partials, then the final values
     L.dirs = take(MAX_DIRS * 3 * 8);
     L.out = take((RED_VALUES + MAX_DIRS) * 8);
+    L.wall = p->walls ? take(N) : 0;
     L.total = off;
     return L;
 }
@@ -128,6 +129,7 @@ struct Tiling {
     int aux;        // store cache policy
     int laux = 0;   // cache policy of the single-use loads (g, f, phi_prev)
     int zband = 0;  // z tile-layers per band of the block tile order (0: plain x, y, z order)
+    bool walls = false;  // the kernel honours the solid-wall mask
 };
 
 InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling& T) {
@@ -149,6 +151,7 @@ InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling&
         I.f[k] = p->flow ? ws + L.f[k] : nullptr;
     }
     I.phi_prev = ws + L.phi_prev;
+    I.wall = p->walls ? reinterpret_cast<const unsigned char*>(ws + L.wall) : nullptr;
     I.k = p->W0 * p->W0 / p->tau0;
     I.inv_tau0 = 1.0 / p->tau0;
     I.lambda = p->lambda;
@@ -245,16 +248,18 @@ struct CommonOps {
 };
 
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
-          int LAUX = 0>
+          int LAUX = 0, bool WALLS = false>
 struct BlockOps : CommonOps<DIM, FLOW, real, fst> {
     using C = CommonOps<DIM, FLOW, real, fst>;
     static void step(const InstDev& I, int par, hipStream_t s) {
         const int nblocks = I.tiles_x * I.tiles_y * I.tiles_z;
-        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX>), dim3(nblocks),
+        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS>), dim3(nblocks),
                            dim3(TX * TY * TZ), 0, s, I, par);
     }
     static Ops ops() {
-        return Ops{Tiling{false, TX, TY, TZ, PF, AUX, LAUX, 0}, step, C::init, C::field, C::reduce, C::ray};
+        Tiling t{false, TX, TY, TZ, PF, AUX, LAUX, 0};
+        t.walls = WALLS;
+        return Ops{t, step, C::init, C::field, C::reduce, C::ray};
     }
 };
 
@@ -338,8 +343,34 @@ void block_variants(std::vector<Variant>& v, bool large) {
     }
 }
 
+// Tilings of the kernel that honours a wall mask (the first is the default).
 template <int DIM, bool FLOW, typename real, typename fst>
-std::vector<Variant> variants_of(int nx, double pop_bytes) {
+std::vector<Variant> wall_variants(bool large) {
+    std::vector<Variant> v;
+    auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
+    if constexpr (DIM == 2) {
+        static const Ops a = BlockOps<2, FLOW, real, fst, 64, 4, 1, false, 0, 0, true>::ops();
+        add(a);
+    } else if constexpr (sizeof(real) == 8) {
+        static const Ops a = BlockOps<3, FLOW, real, fst, 16, 4, 4, false, 0, 0, true>::ops();
+        add(a);
+    } else {
+        static const Ops a = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 0, 0, true>::ops();
+        static const Ops b = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 0, true>::ops();
+        if (large) {
+            add(b);
+            add(a);
+        } else {
+            add(a);
+            add(b);
+        }
+    }
+    return v;
+}
+
+template <int DIM, bool FLOW, typename real, typename fst>
+std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls) {
+    if (walls) return wall_variants<DIM, FLOW, real, fst>(pop_bytes > LLC_BYTES);
     std::vector<Variant> v;
     block_variants<DIM, FLOW, real, fst>(v, pop_bytes > LLC_BYTES);
     if constexpr (DIM == 3) {
@@ -366,18 +397,18 @@ std::vector<Variant> variants_of(int nx, double pop_bytes) {
 }
 
 // Candidate tilings for one grid kind; the first is the default. pop_bytes: both population copies.
-std::vector<Variant> variants_for(int dim, int flow, int prec, int nx, double pop_bytes) {
+std::vector<Variant> variants_for(int dim, int flow, int prec, int nx, double pop_bytes, bool walls) {
     const double b = pop_bytes;
     if (dim == 2) {
-        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx, b) : variants_of<2, false, float, float>(nx, b);
-        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx, b)
-               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx, b)
-                                   : variants_of<2, true, float, __half>(nx, b);
+        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx, b, walls) : variants_of<2, false, float, float>(nx, b, walls);
+        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx, b, walls)
+               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx, b, walls)
+                                   : variants_of<2, true, float, __half>(nx, b, walls);
     }
-    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx, b) : variants_of<3, false, float, float>(nx, b);
-    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx, b)
-           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx, b)
-                               : variants_of<3, true, float, __half>(nx, b);
+    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx, b, walls) : variants_of<3, false, float, float>(nx, b, walls);
+    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx, b, walls)
+           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx, b, walls)
+                               : variants_of<3, true, float, __half>(nx, b, walls);
 }
 
 double population_bytes(const lbcg_params& p) {
@@ -394,6 +425,7 @@ std::string variant_name(const Variant& v) {
         std::snprintf(buf, sizeof buf, "block %dx%dx%d%s%s%s", t.TX, t.TY, t.TZ, t.prefetch ? " prefetch" : "",
                       t.aux ? " nt-stores" : "", t.laux ? " nt-loads" : "");
         if (t.zband > 1) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " zband %d", t.zband);
+        if (t.walls) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " walls");
     return buf;
 }
 
@@ -522,6 +554,7 @@ void validate_batch(int n, const lbcg_params* p) {
         validate(&p[i]);
         if (p[i].dim != p[0].dim || p[i].flow != p[0].flow || p[i].precision != p[0].precision)
             throw Error(LBCG_EINVAL, "all instances of a batch need the same dim, flow and precision");
+        if (p[i].walls) throw Error(LBCG_EINVAL, "batches do not take walls");
         tiles += (long long)p[i].nx * p[i].ny * p[i].nz;
     }
     if (tiles > (1LL << 31)) throw Error(LBCG_EINVAL, "batch too large");
@@ -594,7 +627,7 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
         hdl->L = L;
         hdl->ws = (char*)dev_workspace;
         hdl->stream = (hipStream_t)hip_stream;
-        hdl->variants = variants_for(p->dim, p->flow, p->precision, p->nx, population_bytes(*p));
+        hdl->variants = variants_for(p->dim, p->flow, p->precision, p->nx, population_bytes(*p), p->walls != 0);
         hdl->variant = 0;
         hdl->ops = hdl->variants[0].ops;
         hdl->inst = make_inst(p, hdl->ws, L, hdl->variants[0].tiling);
@@ -607,6 +640,7 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
                    p->flow ? p->u_inlet : 0.0};
         // unused halves of the ping-pong buffers start defined (zero) so raw reads are reproducible
         HIPCHK(hipMemsetAsync(hdl->ws, 0, L.staging, hdl->stream));
+        if (p->walls) HIPCHK(hipMemsetAsync(hdl->ws + L.wall, 0, (size_t)hdl->inst.N, hdl->stream));
         hdl->ops->init(hdl->inst, 0, a, hdl->stream);
         HIPCHK(hipGetLastError());
     });
@@ -911,6 +945,42 @@ lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_
     });
 }
 
+// ---- solid walls ----
+
+lbcg_status lbcg_set_walls(lbcg_handle* h, const uint8_t* mask, size_t bytes, int mask_on_device) {
+    return guarded([&] {
+        if (!h || !mask) throw Error(LBCG_EINVAL, "NULL handle or mask");
+        if (!h->p.walls) throw Error(LBCG_EINVAL, "the solver was created with walls = 0");
+        const size_t N = (size_t)h->inst.N, nx = (size_t)h->p.nx;
+        if (bytes < N) throw Error(LBCG_EINVAL, "mask smaller than the grid");
+        std::vector<uint8_t> host;
+        const uint8_t* hm = mask;
+        if (mask_on_device) {
+            host.resize(N);
+            HIPCHK(hipMemcpy(host.data(), mask, N, hipMemcpyDeviceToHost));
+            hm = host.data();
+        }
+        if (h->p.xbc == LBCG_INFLOW_OUTFLOW)  // the outlet copy pairs the last two columns of a row
+            for (size_t r = 0; r < N / nx; r++)
+                if ((hm[r * nx + nx - 2] != 0) != (hm[r * nx + nx - 1] != 0))
+                    throw Error(LBCG_EINVAL, "a row's last two columns must be both wall or both fluid");
+        HIPCHK(hipMemcpyAsync(h->ws + h->L.wall, hm, N, hipMemcpyHostToDevice, h->stream));  // hm is host memory
+        // Wall nodes are never written: give both ping-pong copies the current state so that they
+        // stay frozen whichever copy is current.
+        const lbcg_params& p = h->p;
+        const size_t rs = real_size(p.precision), fs = fstore_size(p.precision);
+        const int cur = h->par, oth = h->par ^ 1;
+        HIPCHK(hipMemcpyAsync(h->ws + h->L.h[oth], h->ws + h->L.h[cur], qs_of(p.dim) * N * rs,
+                              hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->ws + h->L.g[oth], h->ws + h->L.g[cur], qs_of(p.dim) * N * rs,
+                              hipMemcpyDeviceToDevice, h->stream));
+        if (p.flow)
+            HIPCHK(hipMemcpyAsync(h->ws + h->L.f[oth], h->ws + h->L.f[cur], qf_of(p.dim) * N * fs,
+                                  hipMemcpyDeviceToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    });
+}
+
 // ---- checkpoints ----
 
 namespace {
@@ -1036,7 +1106,7 @@ lbcg_status lbcg_batch_create(int n, const lbcg_params* p, void* dev_workspace, 
         b->ws = (char*)dev_workspace;
         b->stream = (hipStream_t)hip_stream;
         b->kit = &batch_kit_for(p[0].dim, p[0].flow, p[0].precision);
-        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0)[0].ops;
+        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0, false)[0].ops;
         b->par = 0;
         b->nstep = 0;
         int tiles = 0;

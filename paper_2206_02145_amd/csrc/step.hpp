@@ -56,6 +56,7 @@ struct InstDev {
     void* g[2];
     void* f[2];
     void* phi_prev;
+    const unsigned char* wall;    // solid-wall flags per node (plain layout), or null
     double k;                     // W0^2 / tau0
     double inv_tau0, lambda, eps, grad_eps2, D;
     double tau_f, kdrag;          // kdrag = h_drag tau_f / (4 W0^2)
@@ -117,12 +118,14 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 // LAUX: cache-policy bits of the loads of g, f and phi_prev, which are read once (h keeps the
 // default policy: its halo is read again by the neighbouring tiles).
 //
+// WALLS: honour the solid-wall mask I.wall (zero-flux / no-slip bounce-back, see lbcg_set_walls).
+//
 // Tile order: x fastest, so that the x-neighbours, which share the halo's cache lines, run
 // together. With I.zband = B > 1 the z tile-layers are grouped in bands of B: within a band the
 // order is x, then z, then y, so the tiles above and below run B * tiles_x apart instead of a whole
 // layer apart and the z-halo of h is still in L2 when it is read again.
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
-          int LAUX = 0>
+          int LAUX = 0, bool WALLS = false>
 __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, const int par) {
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
@@ -136,6 +139,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     constexpr bool ROW = (TX == 64);
     __shared__ real s_phi[NB];
     __shared__ real s_h[S::Q][NB];
+    __shared__ unsigned char s_wall[WALLS ? NB : 1];
 
     const int tid = threadIdx.x;
     const int nx = I.nx, ny = I.ny, nz = I.nz;
@@ -226,6 +230,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                     phi += v;
                 }
                 s_phi[b] = phi;
+                if constexpr (WALLS) s_wall[b] = I.wall[rb + (unsigned)ga];
             }
             if (lx < 2) {
                 const int b = r * BX + 64 + lx;
@@ -237,6 +242,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                     phi += v;
                 }
                 s_phi[b] = phi;
+                if constexpr (WALLS) s_wall[b] = I.wall[rb + (unsigned)gb];
             }
         }
     } else {
@@ -257,14 +263,18 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                 phi += v;
             }
             s_phi[b] = phi;
+            if constexpr (WALLS) s_wall[b] = I.wall[rb + (unsigned)gx];
         }
     }
     __syncthreads();
 
     // ---- phase 2: one node per thread ----
     if (!valid) return;
-    if constexpr (!PF) load_own();
     const int bo = (DIM == 3 ? (lz + 1) * SZ : 0) + (ly + 1) * SY + (lx + 1);
+    if constexpr (WALLS) {
+        if (s_wall[bo]) return;  // wall nodes are frozen
+    }
+    if constexpr (!PF) load_own();
 
     // Push targets. Every population is written at memory column x of its destination row, except
     // at an open x face: the inlet node (x = 0) pushes nothing with c_x < 0 (those slots are
@@ -293,11 +303,31 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     const real two_m_psi = (real)2 - psi;  // 1 - phi
     const real p2 = psi * two_m_psi;       // 1 - phi^2
 
+    // directions whose destination inside the domain is a wall node (bit a of swall / vwall)
+    unsigned swall = 0, vwall = 0;
+    if constexpr (WALLS) {
+#pragma unroll
+        for (int a = 1; a < S::Q; a++)
+            if (push_ok(S::c(a, 0)) && s_wall[bo + S::c(a, 0) + S::c(a, 1) * SY + (DIM == 3 ? S::c(a, 2) * SZ : 0)])
+                swall |= 1u << a;
+        if constexpr (FLOW) {
+#pragma unroll
+            for (int a = 1; a < V::Q; a++)
+                if (push_ok(V::c(a, 0)) && s_wall[bo + V::c(a, 0) + V::c(a, 1) * SY + (DIM == 3 ? V::c(a, 2) * SZ : 0)])
+                    vwall |= 1u << a;
+        }
+    }
+    auto to_wall = [](unsigned bits, int a) { return WALLS && ((bits >> a) & 1u) != 0; };
+    // A value bounced back at x = nx - 2 into a population with c_x < 0 is also what the outlet
+    // copy gives node nx - 1 of the same row (memory column 0 there).
+    const bool pre_outlet = WALLS && xopen && x == nx - 2;
+
     // grad phi = (1/cs^2) sum_b w_b c_b phi(x + c_b), D2Q9 / D3Q19 stencil (the shift cancels)
     real px = 0, py = 0, pz = 0;
 #pragma unroll
     for (int b = 1; b < V::Q; b++) {
-        const real ph = s_phi[bo + V::c(b, 0) + V::c(b, 1) * SY + (DIM == 3 ? V::c(b, 2) * SZ : 0)];
+        const int nb = bo + V::c(b, 0) + V::c(b, 1) * SY + (DIM == 3 ? V::c(b, 2) * SZ : 0);
+        const real ph = (WALLS && s_wall[nb]) ? psi : s_phi[nb];  // a wall neighbour: zero normal derivative
         const real wc = (real)(V::w(b) * V::inv_cs2);
         if (V::c(b, 0)) px += (real)V::c(b, 0) * wc * ph;
         if (V::c(b, 1)) py += (real)V::c(b, 1) * wc * ph;
@@ -359,7 +389,19 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
             const real hnb = s_h[a][bo + cx + cy * SY + (DIM == 3 ? cz * SZ : 0)];
             vk[a] = (hk[a] - one_m_a2 * hnb) * inv_a2;
-            if (push_ok(cx)) ST(hout, a, row(cy, cz), x, vk[a]);  // memory column of node x + cx is x
+            if (push_ok(cx) && !to_wall(swall, a)) ST(hout, a, row(cy, cz), x, vk[a]);  // memory column of x + cx is x
+        }
+        if constexpr (WALLS) {
+            if (swall) {  // zero-flux bounce-back off walls, old value of the slot written (as at the inlet)
+#pragma unroll
+                for (int a = 1; a < S::Q; a++)
+                    if (to_wall(swall, a)) {
+                        const int b = S::opp(a);
+                        const real v = (hk[a] - one_m_a2 * s_h[b][bo]) * inv_a2;
+                        ST(hout, b, rowO, xcol(S::c(b, 0)), v);
+                        if (S::c(b, 0) < 0 && pre_outlet) ST(hout, b, rowO, 0, v);
+                    }
+            }
         }
         if (xopen) {
 #pragma unroll
@@ -369,7 +411,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                     const int b = S::opp(a);
                     ST(hout, b, rowO, xcp, (hk[a] - one_m_a2 * s_h[b][bo]) * inv_a2);
                 }
-                if (at_outlet) ST(hout, a, row(S::c(a, 1), S::c(a, 2)), xcm, vk[a]);
+                if (at_outlet && !to_wall(swall, a)) ST(hout, a, row(S::c(a, 1), S::c(a, 2)), xcm, vk[a]);
             }
         }
     }
@@ -416,7 +458,17 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         fk[0] = drho - fsum;  // mass: the collision and the Guo term leave sum_a (f_a - w_a) = rho - 1
 #pragma unroll
         for (int a = 0; a < V::Q; a++)
-            if (push_ok(V::c(a, 0))) ST(fout, a, row(V::c(a, 1), V::c(a, 2)), x, fk[a]);
+            if (push_ok(V::c(a, 0)) && !to_wall(vwall, a)) ST(fout, a, row(V::c(a, 1), V::c(a, 2)), x, fk[a]);
+        if constexpr (WALLS) {
+            if (vwall) {  // no-slip halfway bounce-back off walls at rest
+#pragma unroll
+                for (int a = 1; a < V::Q; a++)
+                    if (to_wall(vwall, a)) {
+                        ST(fout, V::opp(a), rowO, xcol(-V::c(a, 0)), fk[a]);
+                        if (V::c(a, 0) > 0 && pre_outlet) ST(fout, V::opp(a), rowO, 0, fk[a]);
+                    }
+            }
+        }
         if (xopen) {
 #pragma unroll
             for (int a = 0; a < V::Q; a++) {
@@ -424,7 +476,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                 if (cx >= 0) continue;
                 if (at_inlet)  // velocity bounce-back, wall density 1
                     ST(fout, V::opp(a), rowO, xcp, fk[a] - (real)6 * (real)V::w(a) * (real)cx * uinx);
-                if (at_outlet) ST(fout, a, row(V::c(a, 1), V::c(a, 2)), xcm, fk[a]);
+                if (at_outlet && !to_wall(vwall, a)) ST(fout, a, row(V::c(a, 1), V::c(a, 2)), xcm, fk[a]);
             }
         }
     }
@@ -450,23 +502,34 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         gk[0] = (Ut - dphi) - gsum;  // solute balance of the node: sum_a g*_a - U0 = U - U0 - dphi
 #pragma unroll
         for (int a = 0; a < S::Q; a++)
-            if (push_ok(S::c(a, 0))) ST(gout, a, row(S::c(a, 1), S::c(a, 2)), x, gk[a]);
+            if (push_ok(S::c(a, 0)) && !to_wall(swall, a)) ST(gout, a, row(S::c(a, 1), S::c(a, 2)), x, gk[a]);
+        if constexpr (WALLS) {
+            if (swall) {  // zero-flux bounce-back off walls
+#pragma unroll
+                for (int a = 1; a < S::Q; a++)
+                    if (to_wall(swall, a)) {
+                        ST(gout, S::opp(a), rowO, xcol(-S::c(a, 0)), gk[a]);
+                        if (S::c(a, 0) > 0 && pre_outlet) ST(gout, S::opp(a), rowO, 0, gk[a]);
+                    }
+            }
+        }
         if (xopen) {
 #pragma unroll
             for (int a = 0; a < S::Q; a++) {
                 if (S::c(a, 0) >= 0) continue;
                 if (at_inlet)  // anti-bounce-back, U = U_in on the inlet wall
                     ST(gout, S::opp(a), rowO, xcp, -gk[a] + (real)S::w(a) * Uin2);
-                if (at_outlet) ST(gout, a, row(S::c(a, 1), S::c(a, 2)), xcm, gk[a]);
+                if (at_outlet && !to_wall(swall, a)) ST(gout, a, row(S::c(a, 1), S::c(a, 2)), xcm, gk[a]);
             }
         }
     }
     ST(pprev, 0, rowO, xc0, psi);
 }
 
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX>
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX,
+          bool WALLS = false>
 __global__ __launch_bounds__(TX* TY* TZ) void step_single(InstDev I, int par) {
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX>(I, xcd_tile(blockIdx.x, gridDim.x), par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS>(I, xcd_tile(blockIdx.x, gridDim.x), par);
 }
 
 // Batched launch: the tiles of all instances form one list; each workgroup finds its instance

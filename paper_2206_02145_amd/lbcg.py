@@ -27,7 +27,7 @@ class lbcg_params(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("nz", ctypes.c_int32), ("flow", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("xbc", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("xbc", ctypes.c_int32), ("walls", ctypes.c_int32),
         ("W0", ctypes.c_double), ("tau0", ctypes.c_double), ("lambda_", ctypes.c_double),
         ("D", ctypes.c_double), ("eps_aniso", ctypes.c_double), ("nu", ctypes.c_double),
         ("h_drag", ctypes.c_double), ("u_inlet", ctypes.c_double), ("U0", ctypes.c_double),
@@ -67,6 +67,7 @@ def lib():
         L.lbcg_measure.argtypes = [vp, i32, dp, dp, dp]
         L.lbcg_growth_rates.argtypes = [vp, dp, dp, dp]
         L.lbcg_destroy.argtypes = [vp]
+        L.lbcg_set_walls.argtypes = [vp, vp, sz, i32]
         L.lbcg_state_bytes.argtypes = [vp]
         L.lbcg_state_bytes.restype = sz
         L.lbcg_state_save.argtypes = [vp, vp, sz, i32]
@@ -107,7 +108,7 @@ def lib():
                      "lbcg_variant_current", "lbcg_batch_create", "lbcg_batch_run", "lbcg_batch_measure",
                      "lbcg_batch_read_field", "lbcg_batch_destroy", "lbcg_mlp_create", "lbcg_mlp_set_params",
                      "lbcg_mlp_get_params", "lbcg_mlp_forward", "lbcg_mlp_grads", "lbcg_mlp_train_step",
-                     "lbcg_mlp_destroy", "lbcg_state_save", "lbcg_state_load"):
+                     "lbcg_mlp_destroy", "lbcg_state_save", "lbcg_state_load", "lbcg_set_walls"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -122,7 +123,7 @@ def make_params(p: dict, precision: str = "fp32") -> lbcg_params:
     """lbcg_params from a parameter dict (keys as in paper_2206_02145_amd.workloads)."""
     s = lbcg_params()
     s.dim, s.nx, s.ny, s.nz = int(p["dim"]), int(p["nx"]), int(p["ny"]), int(p["nz"])
-    s.flow, s.xbc, s.reserved = int(p["flow"]), int(p["xbc"]), 0
+    s.flow, s.xbc, s.walls = int(p["flow"]), int(p["xbc"]), int(p.get("walls", 0))
     s.precision = PRECISION[precision]
     s.W0, s.tau0, s.lambda_, s.D = p["W0"], p["tau0"], p["lam"], p["D"]
     s.eps_aniso, s.nu, s.h_drag = p["eps"], p["nu"], p["h_drag"]
@@ -203,6 +204,11 @@ class Solver:
             arr = arr.astype(np.float64)
         check(lib().lbcg_write_field(self.handle, FIELD[field], arr.ctypes.data, arr.nbytes, 0,
                                      DTYPE[arr.dtype.type]), "lbcg_write_field")
+
+    def set_walls(self, mask):
+        """Solid wall nodes: nonzero entries of a (nz, ny, nx) mask (the solver needs walls=1)."""
+        m = np.ascontiguousarray(np.broadcast_to(np.asarray(mask) != 0, self.shape), dtype=np.uint8)
+        check(lib().lbcg_set_walls(self.handle, m.ctypes.data, m.nbytes, 0), "lbcg_set_walls")
 
     # ---- checkpoints ----
     def save_state(self, device: bool = False):

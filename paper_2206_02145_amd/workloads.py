@@ -92,3 +92,18 @@ def directions(K: int, dim: int = 2, offset: float = 0.0) -> np.ndarray:
 def paper_face_normals() -> np.ndarray:
     """Six directions at 30 + 60 k degrees (face normals of a hexagon with vertices on the axes)."""
     return directions(6, offset=math.pi / 6)
+
+
+def config3_walls():
+    """The 192x128x128 flow configuration in a walled cell: a floor (z = 0), a side wall (y = 0)
+    and a square baffle plate in front of the seed, normal to the inflow (x = 32, y and z 40 .. 87).
+    Returns (params with walls = 1, wall mask [z][y][x] as uint8). A synthetic stand-in for the
+    reactor geometry, which the paper shows only in figures."""
+    import numpy as np
+    p = dict(config3(), walls=1)
+    m = np.zeros((p["nz"], p["ny"], p["nx"]), np.uint8)
+    m[0, :, :] = 1
+    m[:, 0, :] = 1
+    m[40:88, 40:88, 32] = 1
+    return p, m
+
