@@ -90,7 +90,19 @@ typedef struct {
     double U0, U_inlet;  /* initial and inlet supersaturation */
     double seed_center[3], seed_radius; /* initial seed (node coordinates; z ignored in 2-D) */
     double grad_eps2;    /* |grad phi|^2 at or below which a_s = 1 and the anisotropy flux is 0 */
+    int32_t seed_shape;  /* lbcg_seed_shape; polygons have circumradius seed_radius and are prisms
+                          * of half-height equal to their apothem in 3-D */
+    int32_t reserved;    /* must be 0 */
+    double seed_tilt;    /* rotation of a polygonal seed about z, radians (the paper's seed tilt) */
 } lbcg_params;
+
+/* Seed shapes (Section 4: rhombic and hexagonal seeds, tilted). The initial phase field is
+ * phi0 = tanh(-d / (sqrt(2) W0)) with d the signed distance to the seed: |x - c| - R for the
+ * circle / sphere, and for a polygon the largest distance to its face planes, max_k n_k.(x - c) - a
+ * (apothem a = R cos(pi/n)). Hexagon: face normals at tilt + 30 + 60k degrees (vertices on the axes
+ * at tilt 0); rhombus (60 / 120 degrees): face normals at tilt +- 60 and tilt + 180 +- 60 degrees
+ * (long diagonal, 2R, along the tilt direction). */
+typedef enum { LBCG_SEED_CIRCLE = 0, LBCG_SEED_HEXAGON = 1, LBCG_SEED_RHOMBUS = 2 } lbcg_seed_shape;
 
 typedef struct lbcg_handle lbcg_handle;
 typedef struct lbcg_batch lbcg_batch;

@@ -141,6 +141,7 @@ static int check_params(const orc_params* P) {
     if (P->dim == 2 && P->nz != 1) return -1;
     if (P->xbc == 1 && P->nx < 3) return -1;
     if (P->tau0 <= 0 || P->W0 <= 0) return -1;
+    if (P->seed_shape < 0 || P->seed_shape > 2) return -1;
     return 0;
 }
 
@@ -211,6 +212,29 @@ static void flow_velocity(const orc_params* P, double tau_f, double phi, double 
 /* Initial state (R11, R17, R26)                                                               */
 /* ------------------------------------------------------------------------------------------ */
 
+double orc_seed_distance(const orc_params* P, double dx, double dy, double dz) {
+    const double pi = 3.14159265358979323846;
+    const double R = P->seed_R;
+    if (P->seed_shape == 0) return sqrt(dx * dx + dy * dy + dz * dz) - R;
+    /* hexagon: face normals at 30 + 60 k degrees (vertices on the axes); rhombus: face normals at
+     * +-60 and 180 +-60 degrees (its long diagonal along x); both turned by the tilt */
+    int nf = P->seed_shape == 1 ? 6 : 4;
+    static const double hex_deg[6] = {30, 90, 150, 210, 270, 330};
+    static const double rho_deg[4] = {60, 120, 240, 300};
+    double apothem = R * cos(pi / (P->seed_shape == 1 ? 6.0 : 3.0));
+    double d = -1e300;
+    for (int k = 0; k < nf; k++) {
+        double ang = (P->seed_shape == 1 ? hex_deg[k] : rho_deg[k]) * pi / 180.0 + P->seed_tilt;
+        double dk = cos(ang) * dx + sin(ang) * dy - apothem;
+        if (dk > d) d = dk;
+    }
+    if (P->dim == 3) {
+        double dzk = fabs(dz) - apothem;
+        if (dzk > d) d = dzk;
+    }
+    return d;
+}
+
 int orc_init(const orc_params* P, double* h, double* g, double* f, double* phi_prev) {
     if (check_params(P)) return -1;
     lattice S = scalar_lattice(P->dim);
@@ -223,8 +247,7 @@ int orc_init(const orc_params* P, double* h, double* g, double* f, double* phi_p
             long i = node(P, x, y, z);
             double dx = x - P->seed_c[0], dy = y - P->seed_c[1];
             double dz = (P->dim == 3) ? z - P->seed_c[2] : 0.0;
-            double dist = sqrt(dx * dx + dy * dy + dz * dz);
-            double phi0 = tanh((P->seed_R - dist) / (sqrt(2.0) * P->W0));
+            double phi0 = tanh(-orc_seed_distance(P, dx, dy, dz) / (sqrt(2.0) * P->W0));
             phi_prev[i] = phi0;
             for (int a = 0; a < S.q; a++) {
                 h[a * N + i] = S.w[a] * phi0;

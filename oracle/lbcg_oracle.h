@@ -32,6 +32,9 @@ typedef struct {
     double grad_eps2;                  /* |grad phi|^2 threshold below which a_s = 1, N = 0 */
     const uint8_t* wall;               /* NULL, or one flag per node (1 = solid wall node, R28):
                                         * walls are frozen, populations aimed at them bounce back */
+    int32_t seed_shape;                /* 0 circle / sphere, 1 hexagon, 2 rhombus (60/120 degrees);
+                                        * polygons are prisms in 3-D (R29) */
+    double seed_tilt;                  /* rotation of a polygonal seed about z (radians) */
 } orc_params;
 
 /* Lattice tables. kind: 0 = D2Q5, 1 = D3Q7, 2 = D2Q9, 3 = D3Q19.
@@ -42,7 +45,14 @@ int orc_lattice(int kind, int* q, int* c, double* w, double* cs2);
  * in 2-D). */
 void orc_aniso(double eps, double grad_eps2, const double* p, double* a, double* N);
 
-/* Initial state: tanh seed, h = w phi0, g = w U0, f = f_eq(1, u_in (1-phi0)/2 x^), phi_prev = phi0.
+/* Signed distance of the point (dx, dy, dz) (relative to the seed centre) to the seed's surface,
+ * negative inside: |x| - R for the circle / sphere; for a polygon of circumradius R the largest
+ * distance to its face planes, max_k n_k . x - a (apothem a = R cos(pi/n)), and in 3-D also to the
+ * planes z = +-a (R29). */
+double orc_seed_distance(const orc_params* P, double dx, double dy, double dz);
+
+/* Initial state: tanh seed, h = w phi0, g = w U0, f = f_eq(1, u_in (1-phi0)/2 x^), phi_prev = phi0,
+ * phi0 = tanh(-d / (sqrt(2) W0)) with d = orc_seed_distance.
  * f may be NULL when flow = 0. Returns 0 or -1 on bad parameters. */
 int orc_init(const orc_params* P, double* h, double* g, double* f, double* phi_prev);
 

@@ -34,6 +34,8 @@ class OrcParams(ctypes.Structure):
         ("seed_c", ctypes.c_double * 3), ("seed_R", ctypes.c_double),
         ("grad_eps2", ctypes.c_double),
         ("wall", ctypes.c_void_p),
+        ("seed_shape", ctypes.c_int32),
+        ("seed_tilt", ctypes.c_double),
     ]
 
 
@@ -70,6 +72,8 @@ def lib():
         L.orc_raymarch.argtypes = [pp, dp, ctypes.c_int, dp, dp]
         L.orc_num_threads.argtypes = []
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        L.orc_seed_distance.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_seed_distance.restype = ctypes.c_double
         L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
@@ -93,6 +97,8 @@ def make_params(p: dict) -> OrcParams:
             setattr(s, k, int(v))
         else:
             setattr(s, k, float(v))
+    s.seed_shape = int(p.get("seed_shape", 0))
+    s.seed_tilt = float(p.get("seed_tilt", 0.0))
     return s
 
 
@@ -118,6 +124,11 @@ def aniso(eps: float, p, grad_eps2: float = 1e-12):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def seed_distance(p: dict, dx: float, dy: float, dz: float = 0.0) -> float:
+    cp = make_params(p)
+    return float(lib().orc_seed_distance(ctypes.byref(cp), dx, dy, dz))
 
 
 def set_num_threads(n: int):

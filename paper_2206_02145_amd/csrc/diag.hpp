@@ -12,8 +12,29 @@
 namespace lbcg {
 
 struct SeedArgs {
-    double cx, cy, cz, R, W0, U0, u_in;
+    double cx, cy, cz, R, W0, U0, u_in, tilt;
+    int shape;  // lbcg_seed_shape
 };
+
+// Signed distance to the seed surface (negative inside) for the offset (dx, dy, dz) from its
+// centre: the sphere, or the largest distance to the face planes of the tilted polygon (and, in
+// 3-D, to the planes z = +-apothem of its prism).
+template <int DIM>
+__device__ inline double seed_distance(const SeedArgs& s, double dx, double dy, double dz) {
+    if (s.shape == 0) return sqrt(dx * dx + dy * dy + dz * dz) - s.R;
+    const double pi = 3.141592653589793;
+    const int n = s.shape == 1 ? 6 : 4;
+    const double a = s.R * cos(pi / (s.shape == 1 ? 6 : 3));  // apothem
+    double d = -1e300;
+    for (int k = 0; k < n; k++) {
+        // hexagon: normals at 30 + 60 k degrees; rhombus: 60, 120, 240, 300 degrees
+        const double deg = s.shape == 1 ? 30.0 + 60.0 * k : (k < 2 ? 60.0 + 60.0 * k : 120.0 + 60.0 * k);
+        const double t = deg * (pi / 180.0) + s.tilt;
+        d = fmax(d, cos(t) * dx + sin(t) * dy - a);
+    }
+    if (DIM == 3) d = fmax(d, fabs(dz) - a);
+    return d;
+}
 
 // Initial state: phi0 = tanh((R - |x - c|) / (sqrt(2) W0)), h = w phi0, g = w U0,
 // f = f_eq(rho = 1, u* = u_in (1 - phi0)/2 x^), phi_prev = phi0; evaluated in binary64 and
@@ -33,8 +54,7 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev I, int par, SeedArgs 
         const int z = (int)(r / I.ny);
         const unsigned row = (unsigned)(i - x);
         const double dx = x - s.cx, dy = y - s.cy, dz = (DIM == 3) ? z - s.cz : 0.0;
-        const double d = sqrt(dx * dx + dy * dy + dz * dz);
-        const double phi0 = tanh((s.R - d) / (sqrt(2.0) * s.W0));
+        const double phi0 = tanh(-seed_distance<DIM>(s, dx, dy, dz) / (sqrt(2.0) * s.W0));
         pp.st(0, (unsigned)i, (real)(phi0 + 1.0));
 #pragma unroll
         for (int a = 0; a < S::Q; a++) {

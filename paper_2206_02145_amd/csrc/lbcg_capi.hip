@@ -77,12 +77,14 @@ void validate(const lbcg_params* p) {
     if (p->xbc != LBCG_PERIODIC && p->xbc != LBCG_INFLOW_OUTFLOW) throw Error(LBCG_EINVAL, "unknown xbc");
     if (p->xbc == LBCG_INFLOW_OUTFLOW && p->nx < 3) throw Error(LBCG_EINVAL, "open x faces need nx >= 3");
     if (p->walls != 0 && p->walls != 1) throw Error(LBCG_EINVAL, "walls must be 0 or 1");
+    if (p->seed_shape < LBCG_SEED_CIRCLE || p->seed_shape > LBCG_SEED_RHOMBUS) throw Error(LBCG_EINVAL, "unknown seed shape");
+    if (p->reserved != 0) throw Error(LBCG_EINVAL, "reserved must be 0");
     const double N = (double)p->nx * p->ny * p->nz;
     if (N >= 536870912.0)  // each population plane is addressed with 32-bit byte offsets
         throw Error(LBCG_EINVAL, "grid too large (at most 2^29 - 1 nodes)");
     const double vals[] = {p->W0, p->tau0, p->lambda, p->D, p->eps_aniso, p->nu, p->h_drag,
                            p->u_inlet, p->U0, p->U_inlet, p->seed_center[0], p->seed_center[1],
-                           p->seed_center[2], p->seed_radius, p->grad_eps2};
+                           p->seed_center[2], p->seed_radius, p->grad_eps2, p->seed_tilt};
     for (double v : vals)
         if (!std::isfinite(v)) throw Error(LBCG_EINVAL, "non-finite parameter");
     if (!(p->tau0 > 0) || !(p->W0 > 0))
@@ -637,7 +639,7 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
         hdl->nonfinite = false;
         hdl->hist_ndirs = -1;
         SeedArgs a{p->seed_center[0], p->seed_center[1], p->seed_center[2], p->seed_radius, p->W0, p->U0,
-                   p->flow ? p->u_inlet : 0.0};
+                   p->flow ? p->u_inlet : 0.0, p->seed_tilt, p->seed_shape};
         // unused halves of the ping-pong buffers start defined (zero) so raw reads are reproducible
         HIPCHK(hipMemsetAsync(hdl->ws, 0, L.staging, hdl->stream));
         if (p->walls) HIPCHK(hipMemsetAsync(hdl->ws + L.wall, 0, (size_t)hdl->inst.N, hdl->stream));
@@ -1125,7 +1127,7 @@ lbcg_status lbcg_batch_create(int n, const lbcg_params* p, void* dev_workspace, 
                               b->stream));
         for (int i = 0; i < n; i++) {
             SeedArgs a{p[i].seed_center[0], p[i].seed_center[1], p[i].seed_center[2], p[i].seed_radius, p[i].W0,
-                       p[i].U0, p[i].flow ? p[i].u_inlet : 0.0};
+                       p[i].U0, p[i].flow ? p[i].u_inlet : 0.0, p[i].seed_tilt, p[i].seed_shape};
             b->common->init(b->inst[i], 0, a, b->stream);
         }
         HIPCHK(hipGetLastError());

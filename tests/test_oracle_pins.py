@@ -644,3 +644,39 @@ def test_walls_conserve_solute_and_mass(orc):
     assert abs(f["rho"][fl].sum() - rho0) < 1e-12 * rho0
     assert f["phi"].max() > 0.9  # the seed is still there and growing
 
+
+# --------------------------------------------------------------------------------------------
+# Faceted seeds and habit diagnostics (Section 4: rhombic / hexagonal seeds, tilt, quality Q,
+# aspect ratio; reading R29)
+# --------------------------------------------------------------------------------------------
+
+def test_faceted_seed_geometry(orc):
+    """The initial hexagon lies at its apothem along its face normals and at its circumradius
+    along its vertices (Q = 1, aspect 2/sqrt3); the 60/120 rhombus has aspect sqrt3; a hexagon
+    tilted by pi/3 is the same seed; across a face the profile is the planar tanh of the model."""
+    from paper_2206_02145_amd import habit as H
+    R = 20.0
+    base = dict(dim=2, nx=96, ny=96, seed_c=(48, 48, 0), seed_R=R)
+    hexa = orc.Sim(W.params(**base, seed_shape=1))
+    h = H.from_extents(hexa.measure(H.habit_directions())[0])
+    assert np.abs(h["L"] - R * math.cos(math.pi / 6)).max() < 0.01
+    assert abs(h["Q"] - 1) < 1e-3 and abs(h["aspect"] - 2 / math.sqrt(3)) < 1e-3
+    rh = orc.Sim(W.params(**base, seed_shape=2))
+    assert abs(H.from_extents(rh.measure(H.habit_directions())[0])["aspect"] - math.sqrt(3)) < 1e-3
+    turned = orc.Sim(W.params(**base, seed_shape=1, seed_tilt=math.pi / 3))
+    assert np.abs(turned.phi_prev - hexa.phi_prev).max() < 1e-12
+    # along +y (the normal of the face at 90 degrees) phi0 = tanh(-(k - apothem) / (sqrt2 W0))
+    k = np.arange(10, 30)
+    a = R * math.cos(math.pi / 6)
+    prof = hexa.phi_prev[0, 48 + k, 48]
+    assert np.abs(prof - np.tanh(-(k - a) / (math.sqrt(2) * W.BASE["W0"]))).max() < 1e-14
+
+
+def test_habit_numbers():
+    from paper_2206_02145_amd import habit as H
+    d = H.habit_directions(0.3)
+    assert d.shape == (10, 3) and np.allclose(np.linalg.norm(d, axis=1), 1)
+    assert np.allclose(np.degrees(np.arctan2(d[:6, 1], d[:6, 0])) % 360, (np.degrees(0.3) + 30 + 60 * np.arange(6)) % 360)
+    h = H.from_extents([2, 3, 4, 4, 3, 2, 10, 6, 4, 4])
+    assert h["Q"] == 2.0 and h["aspect"] == 2.0 and h["L_avg"] == 3.0
+
