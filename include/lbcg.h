@@ -56,7 +56,14 @@ typedef enum {
     LBCG_FP32_F16SHIFT = 2 /* as FP32, but the flow populations are stored as binary16 f_a - w_a */
 } lbcg_precision;
 
-typedef enum { LBCG_PERIODIC = 0, LBCG_INFLOW_OUTFLOW = 1 } lbcg_xbc;
+/* x faces: periodic; inlet at x = 0 (velocity bounce-back for f, anti-bounce-back U = U_inlet for
+ * g, bounce-back for h) and a zero-gradient outlet at x = nx-1 (the incoming populations copied from
+ * x = nx-2); or the same inlet with a pressure outlet for the flow: populations leaving through
+ * x = nx-1 come back by anti-bounce-back at rho = 1 and the node's own u*,
+ * f_opp(a) = -f*_a + 2 w_a (1 + (c_a.u*)^2/(2 cs^4) - |u*|^2/(2 cs^2)), while g and h keep the copy.
+ * The zero-gradient outlet fixes no pressure level; with walls or drag along the way the density
+ * then creeps up, which the pressure outlet prevents. */
+typedef enum { LBCG_PERIODIC = 0, LBCG_INFLOW_OUTFLOW = 1, LBCG_INFLOW_PRESSURE = 2 } lbcg_xbc;
 
 typedef enum {
     LBCG_FIELD_PHI = 0,      /* phi = sum h */

@@ -139,7 +139,8 @@ static int check_params(const orc_params* P) {
     if (P->dim != 2 && P->dim != 3) return -1;
     if (P->nx < 1 || P->ny < 1 || P->nz < 1) return -1;
     if (P->dim == 2 && P->nz != 1) return -1;
-    if (P->xbc == 1 && P->nx < 3) return -1;
+    if (P->xbc < 0 || P->xbc > 2) return -1;
+    if (P->xbc != 0 && P->nx < 3) return -1;
     if (P->tau0 <= 0 || P->W0 <= 0) return -1;
     if (P->seed_shape < 0 || P->seed_shape > 2) return -1;
     return 0;
@@ -429,6 +430,12 @@ static void collide_stream(const orc_params* P, const double* h, const double* g
                         s->fn[b * N + i] = fstar - 2.0 * V.w[a] * 1.0 * cuw / V.cs2;
                     } else if (where == 3) { /* no-slip halfway bounce-back at a wall at rest (R28) */
                         s->fn[opposite(&V, a) * N + i] = fstar;
+                    } else if (where == 2 && P->xbc == 2) { /* pressure outlet, rho = 1 (R30):
+                                                              * anti-bounce-back at the node's u* */
+                        double cu = V.c[a][0] * us[0] + V.c[a][1] * us[1] + V.c[a][2] * us[2];
+                        double uu = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+                        s->fn[opposite(&V, a) * N + i] =
+                            -fstar + 2.0 * V.w[a] * 1.0 * (1.0 + cu * cu / (2.0 * V.cs2 * V.cs2) - uu / (2.0 * V.cs2));
                     }
                 }
             }
@@ -503,10 +510,10 @@ int orc_step(const orc_params* P, double* h, double* g, double* f, double* phi_p
         moments(P, h, g, f, &s);
         gradient(P, &s);
         collide_stream(P, h, g, f, phi_prev, &s);
-        if (P->xbc == 1) {
+        if (P->xbc != 0) {
             outlet_fill(P, &S, s.hn);
             outlet_fill(P, &S, s.gn);
-            if (P->flow) outlet_fill(P, &V, s.fn);
+            if (P->flow && P->xbc == 1) outlet_fill(P, &V, s.fn);
         }
         memcpy(h, s.hn, sizeof(double) * S.q * N);
         memcpy(g, s.gn, sizeof(double) * S.q * N);

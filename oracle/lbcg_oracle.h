@@ -25,7 +25,8 @@ typedef struct {
     int32_t dim;          /* 2 or 3 */
     int32_t nx, ny, nz;   /* grid; nz = 1 in 2-D */
     int32_t flow;         /* 1: flow lattice (D2Q9 / D3Q19) active; 0: u* = 0 */
-    int32_t xbc;          /* 0: periodic in x; 1: inlet at x = 0, outlet at x = nx-1 */
+    int32_t xbc;          /* 0: periodic in x; 1: inlet at x = 0, zero-gradient outlet at x = nx-1;
+                           * 2: as 1 with a pressure outlet (rho = 1) for the flow (R30) */
     double W0, tau0, lambda, D, eps;   /* phase-field width, time, coupling, diffusivity, anisotropy */
     double nu, h_drag, u_in, U0, U_in; /* viscosity, drag constant, inlet velocity, initial / inlet U */
     double seed_c[3], seed_R;          /* seed centre (node coordinates) and radius */

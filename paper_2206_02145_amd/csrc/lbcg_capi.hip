@@ -74,8 +74,9 @@ void validate(const lbcg_params* p) {
         throw Error(LBCG_EINVAL, "unknown precision");
     if (p->precision == LBCG_FP32_F16SHIFT && !p->flow)
         throw Error(LBCG_EINVAL, "the binary16 shifted storage applies to the flow populations (flow = 1)");
-    if (p->xbc != LBCG_PERIODIC && p->xbc != LBCG_INFLOW_OUTFLOW) throw Error(LBCG_EINVAL, "unknown xbc");
-    if (p->xbc == LBCG_INFLOW_OUTFLOW && p->nx < 3) throw Error(LBCG_EINVAL, "open x faces need nx >= 3");
+    if (p->xbc != LBCG_PERIODIC && p->xbc != LBCG_INFLOW_OUTFLOW && p->xbc != LBCG_INFLOW_PRESSURE)
+        throw Error(LBCG_EINVAL, "unknown xbc");
+    if (p->xbc != LBCG_PERIODIC && p->nx < 3) throw Error(LBCG_EINVAL, "open x faces need nx >= 3");
     if (p->walls != 0 && p->walls != 1) throw Error(LBCG_EINVAL, "walls must be 0 or 1");
     if (p->seed_shape < LBCG_SEED_CIRCLE || p->seed_shape > LBCG_SEED_RHOMBUS) throw Error(LBCG_EINVAL, "unknown seed shape");
     if (p->reserved != 0) throw Error(LBCG_EINVAL, "reserved must be 0");
@@ -139,7 +140,8 @@ InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling&
     I.nx = p->nx;
     I.ny = p->ny;
     I.nz = p->nz;
-    I.xopen = p->xbc == LBCG_INFLOW_OUTFLOW;
+    I.xopen = p->xbc != LBCG_PERIODIC;
+    I.xpress = p->xbc == LBCG_INFLOW_PRESSURE;
     I.tiles_x = T.march ? 1 : (p->nx + T.TX - 1) / T.TX;
     I.tiles_y = (p->ny + T.TY - 1) / T.TY;
     I.tiles_z = p->dim == 3 ? (p->nz + T.TZ - 1) / T.TZ : 1;
@@ -376,7 +378,7 @@ std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls) {
     std::vector<Variant> v;
     block_variants<DIM, FLOW, real, fst>(v, pop_bytes > LLC_BYTES);
     if constexpr (DIM == 3) {
-        if (nx <= MARCH_MAX_NX) {
+        if (nx > 0 && nx <= MARCH_MAX_NX) {  // (nx = 0: not offered)
             // z-marching kernels (rows of up to 256 nodes) as further candidates
             const int zcs[] = {8, 16, 4, 32};
             for (int zc : zcs) {
@@ -629,7 +631,8 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
         hdl->L = L;
         hdl->ws = (char*)dev_workspace;
         hdl->stream = (hipStream_t)hip_stream;
-        hdl->variants = variants_for(p->dim, p->flow, p->precision, p->nx, population_bytes(*p), p->walls != 0);
+        hdl->variants = variants_for(p->dim, p->flow, p->precision, p->xbc == LBCG_INFLOW_PRESSURE ? 0 : p->nx,
+                                     population_bytes(*p), p->walls != 0);  // (nx 0: no z-marching tiling)
         hdl->variant = 0;
         hdl->ops = hdl->variants[0].ops;
         hdl->inst = make_inst(p, hdl->ws, L, hdl->variants[0].tiling);
@@ -962,7 +965,7 @@ lbcg_status lbcg_set_walls(lbcg_handle* h, const uint8_t* mask, size_t bytes, in
             HIPCHK(hipMemcpy(host.data(), mask, N, hipMemcpyDeviceToHost));
             hm = host.data();
         }
-        if (h->p.xbc == LBCG_INFLOW_OUTFLOW)  // the outlet copy pairs the last two columns of a row
+        if (h->p.xbc != LBCG_PERIODIC)  // the outlet copy pairs the last two columns of a row
             for (size_t r = 0; r < N / nx; r++)
                 if ((hm[r * nx + nx - 2] != 0) != (hm[r * nx + nx - 1] != 0))
                     throw Error(LBCG_EINVAL, "a row's last two columns must be both wall or both fluid");

@@ -48,6 +48,7 @@ namespace lbcg {
 // Per-instance descriptor, shared by the single-grid and the batched launches.
 struct InstDev {
     int nx, ny, nz, xopen;
+    int xpress;                   // the outlet of the flow is a pressure (rho = 1) outlet
     int tiles_x, tiles_y, tiles_z, tile_begin;
     int zc;                       // planes per workgroup of the z-marching kernel
     int zband;                    // block tiles: z tile-layers per band of the tile order (<= 1: none)
@@ -465,7 +466,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                 for (int a = 1; a < V::Q; a++)
                     if (to_wall(vwall, a)) {
                         ST(fout, V::opp(a), rowO, xcol(-V::c(a, 0)), fk[a]);
-                        if (V::c(a, 0) > 0 && pre_outlet) ST(fout, V::opp(a), rowO, 0, fk[a]);
+                        if (V::c(a, 0) > 0 && pre_outlet && !I.xpress) ST(fout, V::opp(a), rowO, 0, fk[a]);
                     }
             }
         }
@@ -476,7 +477,17 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                 if (cx >= 0) continue;
                 if (at_inlet)  // velocity bounce-back, wall density 1
                     ST(fout, V::opp(a), rowO, xcp, fk[a] - (real)6 * (real)V::w(a) * (real)cx * uinx);
-                if (at_outlet && !to_wall(vwall, a)) ST(fout, a, row(V::c(a, 1), V::c(a, 2)), xcm, fk[a]);
+                if (at_outlet && !I.xpress && !to_wall(vwall, a)) ST(fout, a, row(V::c(a, 1), V::c(a, 2)), xcm, fk[a]);
+            }
+            if (I.xpress && at_outlet) {  // pressure outlet: anti-bounce-back at rho = 1 and the node's u*
+#pragma unroll
+                for (int a = 0; a < V::Q; a++) {
+                    const int cx = V::c(a, 0);
+                    if (cx <= 0) continue;
+                    const real cu = (real)cx * usx + (real)V::c(a, 1) * usy + (real)V::c(a, 2) * usz;
+                    // f_opp - w = -(f*_a - w) + 2 w (cu^2 / (2 cs^4) - uu / (2 cs^2))
+                    ST(fout, V::opp(a), rowO, xcm, -fk[a] + (real)2 * (real)V::w(a) * ((real)4.5 * cu * cu - (real)1.5 * uu));
+                }
             }
         }
     }

@@ -1,5 +1,6 @@
-"""Solid walls (reactor walls and baffles: zero-flux phase field and solute, no-slip flow) on the GPU
-against the oracle, through the C ABI (lbcg_set_walls)."""
+"""Solid walls (reactor walls and baffles: zero-flux phase field and solute, no-slip flow) and the
+pressure outlet (rho = 1 anti-bounce-back) on the GPU against the oracle, through the C ABI
+(lbcg_set_walls)."""
 import numpy as np
 import pytest
 
@@ -105,6 +106,51 @@ def test_walls_3d_box_with_baffle_every_variant(lb, orc, prec):
         else:
             for key in state:
                 assert relerr(state[key], ref[key]) < (1e-12 if prec == "fp64" else 1e-5), (names[k], key)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16shift"])
+def test_pressure_outlet_2d_channel_with_baffle(lb, orc, prec):
+    p, m = channel_2d()
+    errs, _ = compare(lb, orc, dict(p, xbc=2), m, prec, 400)
+    for k, v in errs.items():
+        assert v <= TOL[prec], (prec, k, v)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pressure_outlet_3d_box_every_variant(lb, orc, prec):
+    p, m = box_3d()
+    p = dict(p, xbc=2)
+    s = lb.Solver(dict(p, walls=1), prec)
+    names = s.variants()
+    s.close()
+    assert not any(n.startswith("march") for n in names)
+    for k in range(len(names)):
+        errs, _ = compare(lb, orc, p, m, prec, 120, variant=k)
+        for key, v in errs.items():
+            assert v <= TOL[prec], (prec, names[k], key, v)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pressure_outlet_without_walls_single_and_batched(lb, orc, prec):
+    """A seed in the free stream with the pressure outlet, as one grid and inside a batch."""
+    p = W.params(dim=3, nx=40, ny=24, nz=24, flow=1, xbc=2, u_in=0.03, U0=0.3, U_in=0.3,
+                 seed_c=(16.0, 12.0, 12.0), seed_R=5.0)
+    steps = 150
+    ref = orc.Sim(p)
+    ref.step(steps)
+    rf = ref.fields()
+    s = lb.Solver(p, prec)
+    s.step(steps)
+    b = lb.Batch([dict(p, U0=0.2, U_in=0.2), p], prec)
+    b.run(steps)
+    for k in ("phi", "U", "rho", "ux", "uy", "uz"):
+        scale = max(np.abs(rf[k]).max(), 1e-3)
+        e1 = float(np.abs(s.read(k) - rf[k]).max()) / scale
+        e2 = float(np.abs(b.read(1, k) - rf[k]).max()) / scale
+        print(f"[pressure outlet] 3-D {prec} {k}: single {e1:.2e}, batched {e2:.2e}", flush=True)
+        assert e1 <= TOL[prec] and e2 <= TOL[prec], (k, e1, e2)
+    s.close()
+    b.close()
 
 
 def test_walls_keep_solute_plus_solid_in_binary32(lb):

@@ -622,6 +622,38 @@ def test_channel_between_walls_develops_poiseuille(orc):
     assert np.abs(uy + uy[::-1]).max() < 1e-15 and np.abs(uy).max() < 1e-2 * ux.max()  # mirror symmetry
 
 
+def test_pressure_outlet_gives_steady_channel_flow(orc):
+    """With the rho = 1 anti-bounce-back outlet the walled channel reaches a steady state: every
+    cross-section carries the inflow's mass flux rho u_x = u_in (ny - 2), the density next to the
+    outlet is 1, and the downstream profile is the Poiseuille parabola. Without walls the plug flow
+    at density 1 is an exact fixed point."""
+    ny, nx = 18, 64
+    p = W.params(dim=2, nx=nx, ny=ny, flow=1, xbc=2, u_in=0.02, U0=0.1, U_in=0.1, seed_R=-1e9)
+    s = orc.Sim(p)
+    m = np.zeros((1, ny, nx), np.uint8)
+    m[0, 0, :] = m[0, ny - 1, :] = 1
+    s.set_walls(m)
+    s.set_flow_equilibrium(1.0, 0.0, 0.0)
+    s.step(6000)
+    f = s.fields()
+    H = ny - 2
+    flux = (f["rho"] * f["ux"])[0, 1:ny - 1, :].sum(axis=0)
+    assert np.abs(flux[1:] / (0.02 * H) - 1).max() < 1e-6
+    assert abs(f["rho"][0, 1:ny - 1, nx - 1].mean() - 1) < 1e-5
+    y = np.arange(1, ny - 1) - 0.5
+    ux = f["ux"][0, 1:ny - 1, 48]
+    par = 6 * ux.mean() * y * (H - y) / H ** 2
+    assert np.abs(ux - par).max() < 5e-3 * ux.max()
+    s.step(500)
+    assert np.abs(s.fields()["ux"] - f["ux"]).max() < 1e-7  # steady (the transient decays ~10x per 1000 steps)
+
+    p = W.params(dim=2, nx=48, ny=4, flow=1, xbc=2, u_in=0.02, U0=0.1, U_in=0.1, seed_R=-1e9)
+    s = orc.Sim(p)
+    s.step(50)
+    fl = s.fields()
+    assert np.abs(fl["ux"] - 0.02).max() < 1e-15 and np.abs(fl["rho"] - 1).max() < 1e-14
+
+
 def test_walls_conserve_solute_and_mass(orc):
     """A box closed by wall rows (zero flux for U, no-slip for f): the solute-plus-solid invariant
     and the fluid mass stay exact while a seed grows and a shear flow decays against the walls."""
