@@ -28,7 +28,7 @@
  *   bounce-back for f, anti-bounce-back Dirichlet for g, bounce-back for h; outlet: unknown
  *   populations copied from x = nx-2; R17 equilibrium initial populations; R23 gradient ghost at
  *   an open face = copy of the face node; R27 the h bounce-back at the inlet uses the old value of
- *   the slot it writes.
+ *   the slot it writes; R30 optional pressure outlet; R31 the central-Hermite MRT flow collision.
  *
  * Units: lattice units, delta_t = delta_r = 1. Layout: pop[a][z][y][x], x fastest.
  */
@@ -143,6 +143,8 @@ static int check_params(const orc_params* P) {
     if (P->xbc != 0 && P->nx < 3) return -1;
     if (P->tau0 <= 0 || P->W0 <= 0) return -1;
     if (P->seed_shape < 0 || P->seed_shape > 2) return -1;
+    if (P->collision < 0 || P->collision > 1) return -1;
+    if (P->collision == 1 && !(P->omega_bulk > 0.0 && P->omega_bulk < 2.0)) return -1;
     return 0;
 }
 
@@ -207,6 +209,115 @@ static void flow_velocity(const orc_params* P, double tau_f, double phi, double 
         F[d] = -K * u[d];
         us[d] = 0.5 * (1.0 - phi) * u[d];
     }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Central-Hermite multiple-relaxation-time flow collision (the stabilised collision Section 2.2 */
+/* names for the flow; its moment set and relaxation rates are reading R31)                      */
+/* ------------------------------------------------------------------------------------------ */
+
+/* The lattice's Hermite multi-indices (n_x, n_y, n_z), each n_d in {0, 1, 2}: the nine with
+ * n_z = 0 on D2Q9, and on D3Q19 the nineteen with at most two non-zero entries. Returns their
+ * number (= q). */
+static int chm_basis(int dim, int n[19][3]) {
+    int m = 0;
+    for (int a = 0; a <= 2; a++)
+        for (int b = 0; b <= 2; b++)
+            for (int c = 0; c <= (dim == 3 ? 2 : 0); c++)
+                if ((a > 0) + (b > 0) + (c > 0) <= 2) {
+                    n[m][0] = a;
+                    n[m][1] = b;
+                    n[m][2] = c;
+                    m++;
+                }
+    return m;
+}
+
+/* One-dimensional Hermite polynomials of variance cs2: He0 = 1, He1 = xi, He2 = xi^2 - cs2. */
+static double he(int n, double xi, double cs2) { return n == 0 ? 1.0 : (n == 1 ? xi : xi * xi - cs2); }
+
+/* Solve A x = b for an n x n row-major A by Gaussian elimination with partial pivoting
+ * (A and b are overwritten). */
+static void solve_dense(int n, double* A, double* b, double* x) {
+    for (int k = 0; k < n; k++) {
+        int p = k;
+        for (int r = k + 1; r < n; r++)
+            if (fabs(A[r * n + k]) > fabs(A[p * n + k])) p = r;
+        if (p != k) {
+            for (int c = 0; c < n; c++) {
+                double t = A[k * n + c];
+                A[k * n + c] = A[p * n + c];
+                A[p * n + c] = t;
+            }
+            double t = b[k];
+            b[k] = b[p];
+            b[p] = t;
+        }
+        for (int r = k + 1; r < n; r++) {
+            double l = A[r * n + k] / A[k * n + k];
+            for (int c = k; c < n; c++) A[r * n + c] -= l * A[k * n + c];
+            b[r] -= l * b[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; k--) {
+        double s = b[k];
+        for (int c = k + 1; c < n; c++) s -= A[k * n + c] * x[c];
+        x[k] = s / A[k * n + k];
+    }
+}
+
+/* Post-collision populations of one node (f: the node's q populations). Central Hermite moments
+ * about u*: k_n = sum_a f_a prod_d He_{n_d}(c_{a,d} - u*_d). Order 0 is kept (rho); order 1 becomes
+ * (1 - omega) k + (1 - omega/2) F, the momentum update of the BGK scheme with Guo forcing; of the
+ * order-2 tensor the deviatoric part relaxes with omega = 1/tau_f and the trace with omega_bulk;
+ * orders 3 and 4 are set to their equilibrium value 0. The forcing enters the first order only
+ * (its central moments vanish from the second order on). The populations solve T f* = k*. */
+static void chm_collide(const orc_params* P, const lattice* V, const double* f, const double* us,
+                        const double* F, double omega, double* fstar) {
+    int n[19][3];
+    int q = chm_basis(P->dim, n);
+    double T[19 * 19], k[19];
+    for (int m = 0; m < q; m++) {
+        k[m] = 0.0;
+        for (int a = 0; a < q; a++) {
+            double t = 1.0;
+            for (int d = 0; d < 3; d++) t *= he(n[m][d], V->c[a][d] - us[d], V->cs2);
+            T[m * q + a] = t;
+            k[m] += t * f[a];
+        }
+    }
+    /* the order-2 tensor, its trace over the dim active directions */
+    double K2[3][3] = {{0}};
+    for (int m = 0; m < q; m++) {
+        int order = n[m][0] + n[m][1] + n[m][2];
+        if (order != 2) continue;
+        int d = -1, e = -1;
+        for (int j = 0; j < 3; j++)
+            for (int r = 0; r < n[m][j]; r++) {
+                if (d < 0) d = j;
+                else e = j;
+            }
+        K2[d][e] = K2[e][d] = k[m];
+    }
+    double tr = 0.0;
+    for (int d = 0; d < P->dim; d++) tr += K2[d][d];
+    tr /= P->dim;
+    double ks[19];
+    for (int m = 0; m < q; m++) {
+        int order = n[m][0] + n[m][1] + n[m][2];
+        if (order == 0) {
+            ks[m] = k[m];
+        } else if (order == 1) {
+            int d = n[m][0] ? 0 : (n[m][1] ? 1 : 2);
+            ks[m] = (1.0 - omega) * k[m] + (1.0 - 0.5 * omega) * F[d];
+        } else if (order == 2) {
+            int diag = n[m][0] == 2 || n[m][1] == 2 || n[m][2] == 2;
+            ks[m] = diag ? (1.0 - omega) * (k[m] - tr) + (1.0 - P->omega_bulk) * tr : (1.0 - omega) * k[m];
+        } else {
+            ks[m] = 0.0;
+        }
+    }
+    solve_dense(q, T, ks, fstar);
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -416,10 +527,17 @@ static void collide_stream(const orc_params* P, const double* h, const double* g
                 double m[3] = {s->mx[i], s->my[i], s->mz[i]};
                 double u[3], F[3];
                 flow_velocity(P, tau_f, phi, rho, m, u, F, us);
+                double fc[19];
+                if (P->collision == 1) { /* central-Hermite MRT (R31) */
+                    double fl[19];
+                    for (int a = 0; a < V.q; a++) fl[a] = f[a * N + i];
+                    chm_collide(P, &V, fl, us, F, 1.0 / tau_f, fc);
+                }
                 for (int a = 0; a < V.q; a++) {
                     double fa = f[a * N + i];
-                    double fstar = fa - (fa - flow_feq(&V, a, rho, us)) / tau_f +
-                                   guo_source(&V, a, tau_f, us, F);
+                    double fstar = P->collision == 1 ? fc[a]
+                                                     : fa - (fa - flow_feq(&V, a, rho, us)) / tau_f +
+                                                           guo_source(&V, a, tau_f, us, F);
                     long d;
                     int where = destination(P, &V, a, x, y, z, &d);
                     if (where == 0) {

@@ -36,6 +36,9 @@ typedef struct {
     int32_t seed_shape;                /* 0 circle / sphere, 1 hexagon, 2 rhombus (60/120 degrees);
                                         * polygons are prisms in 3-D (R29) */
     double seed_tilt;                  /* rotation of a polygonal seed about z (radians) */
+    int32_t collision;                 /* flow collision: 0 BGK, 1 central-Hermite MRT (R31) */
+    double omega_bulk;                 /* MRT relaxation rate of the trace of the second-order
+                                        * central moment, in (0, 2) */
 } orc_params;
 
 /* Lattice tables. kind: 0 = D2Q5, 1 = D3Q7, 2 = D2Q9, 3 = D3Q19.

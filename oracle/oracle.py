@@ -36,6 +36,8 @@ class OrcParams(ctypes.Structure):
         ("wall", ctypes.c_void_p),
         ("seed_shape", ctypes.c_int32),
         ("seed_tilt", ctypes.c_double),
+        ("collision", ctypes.c_int32),
+        ("omega_bulk", ctypes.c_double),
     ]
 
 
@@ -99,6 +101,8 @@ def make_params(p: dict) -> OrcParams:
             setattr(s, k, float(v))
     s.seed_shape = int(p.get("seed_shape", 0))
     s.seed_tilt = float(p.get("seed_tilt", 0.0))
+    s.collision = int(p.get("collision", 0))
+    s.omega_bulk = float(p.get("omega_bulk", 1.0))
     return s
 
 

@@ -654,6 +654,198 @@ def test_pressure_outlet_gives_steady_channel_flow(orc):
     assert np.abs(fl["ux"] - 0.02).max() < 1e-15 and np.abs(fl["rho"] - 1).max() < 1e-14
 
 
+# --------------------------------------------------------------------------------------------
+# Central-Hermite MRT flow collision (R31)
+# --------------------------------------------------------------------------------------------
+
+def _chm_raw_moments(rho, m, us, F, Pi, omega, omega_b, cs2, dim):
+    """Raw moments of the post-collision populations written out by hand from the relaxation rule
+    (central Hermite moments about u*: order 1 to (1 - w) k + (1 - w/2) F, the deviatoric order-2
+    part with w, its trace with omega_b, orders 3 and 4 to 0), shifted back to raw moments with the
+    binomial expansion of c = (c - u*) + u*. Returns M1, M2, M3[i][j] = sum c_i^2 c_j (i != j) and
+    M4[i][j] = sum c_i^2 c_j^2 (i != j)."""
+    u = us
+    D = np.diag([1.0] * dim + [0.0] * (3 - dim))
+    k1 = m - rho * u
+    K1 = (1 - omega) * k1 + (1 - omega / 2) * F
+    H2 = Pi - np.outer(u, m) - np.outer(m, u) + rho * np.outer(u, u) - rho * cs2 * D
+    t = np.trace(H2) / dim
+    A = (1 - omega) * (H2 - t * D) + (1 - omega_b) * t * D
+    K2 = A + rho * cs2 * D
+    M1 = K1 + rho * u
+    M2 = K2 + np.outer(u, K1) + np.outer(K1, u) + rho * np.outer(u, u)
+    M3, M4 = np.zeros((3, 3)), np.zeros((3, 3))
+    for i in range(dim):
+        for j in range(dim):
+            if i == j:
+                continue
+            Kiij, Kijj = cs2 * K1[j], cs2 * K1[i]
+            Kiijj = cs2 * (K2[i, i] + K2[j, j]) - cs2 ** 2 * rho
+            M3[i, j] = (Kiij + 2 * u[i] * K2[i, j] + u[j] * K2[i, i] + u[i] ** 2 * K1[j]
+                        + 2 * u[i] * u[j] * K1[i] + rho * u[i] ** 2 * u[j])
+            M4[i, j] = (Kiijj + 2 * u[i] * Kijj + 2 * u[j] * Kiij + u[i] ** 2 * K2[j, j] + u[j] ** 2 * K2[i, i]
+                        + 4 * u[i] * u[j] * K2[i, j] + 2 * u[i] * u[j] ** 2 * K1[i] + 2 * u[i] ** 2 * u[j] * K1[j]
+                        + rho * u[i] ** 2 * u[j] ** 2)
+    return M1, M2, M3, M4
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_chmrt_single_node_moments(orc, dim):
+    """One node, random populations: every raw moment the lattice carries (9 on D2Q9, 19 on D3Q19,
+    so the populations themselves) matches the hand-written relaxation rule; with omega_b = 1/tau_f
+    the stress equals that of BGK with Guo forcing."""
+    c_f, w_f, cs2 = orc.lattice(2 if dim == 2 else 3)
+    c_s, w_s, _ = orc.lattice(0 if dim == 2 else 1)
+    rng = np.random.default_rng(10 + dim)
+    for omega_b in (1.0, 0.7, None):
+        p = W.params(dim=dim, nx=1, ny=1, nz=1, flow=1, xbc=0, collision=1, nu=0.02)
+        tau = p["nu"] / cs2 + 0.5
+        p["omega_bulk"] = 1 / tau if omega_b is None else omega_b
+        s = orc.Sim(p, init=False)
+        for trial in range(10):
+            phi = rng.uniform(-0.95, 0.95)
+            s.h[:] = (w_s * phi)[:, None, None, None]
+            s.g[:] = (w_s * 0.1)[:, None, None, None]
+            s.phi_prev[:] = phi
+            s.f[:] = (w_f * (1 + rng.normal(size=len(w_f)) * 0.05))[:, None, None, None]
+            f0 = s.f[:, 0, 0, 0].copy()
+            rho, m = f0.sum(), (c_f * f0[:, None]).sum(0)
+            Pi = np.einsum("a,ai,aj->ij", f0, c_f, c_f)
+            K = p["h_drag"] * tau * (1 + phi) ** 2 * (1 - phi) / (4 * p["W0"] ** 2)
+            u = m / (rho + K / 2)
+            F = -K * u
+            us = (1 - phi) / 2 * u
+            s.step(1)
+            f1 = s.f[:, 0, 0, 0]
+            M1, M2, M3, M4 = _chm_raw_moments(rho, m, us, F, Pi, 1 / tau, p["omega_bulk"], cs2, dim)
+            assert abs(f1.sum() - rho) < 1e-14
+            assert np.abs((c_f * f1[:, None]).sum(0) - M1).max() < 1e-15
+            Pi1 = np.einsum("a,ai,aj->ij", f1, c_f, c_f)
+            assert np.abs(Pi1 - M2).max() < 1e-14
+            for i in range(dim):
+                for j in range(dim):
+                    if i != j:
+                        assert abs((f1 * c_f[:, i] ** 2 * c_f[:, j]).sum() - M3[i, j]) < 1e-14
+                        assert abs((f1 * c_f[:, i] ** 2 * c_f[:, j] ** 2).sum() - M4[i, j]) < 1e-14
+            if omega_b is None:  # all second-order rates 1/tau_f: the BGK-Guo stress
+                I = np.diag([1.0] * dim + [0.0] * (3 - dim))
+                Pi_bgk = ((1 - 1 / tau) * Pi + (rho * cs2 * I + rho * np.outer(us, us)) / tau
+                          + (1 - 1 / (2 * tau)) * (np.outer(us, F) + np.outer(F, us)))
+                assert np.abs(Pi1 - Pi_bgk).max() < 1e-14
+
+
+def test_chmrt_d2q9_tensor_product_form(orc):
+    """On D2Q9 the central moments factorise over x and y, so the post-collision populations are
+    f(i, j) = sum_mn T_im(u_x) T_jn(u_y) K*_mn with T the inverse of the one-dimensional (D1Q3)
+    matrix of central monomials (c - u)^k, k = 0, 1, 2, and K*_mn the post-collision central
+    monomial moments (K*_21 = cs2 K*_01 and K*_22 = cs2 (K*_20 + K*_02) - cs2^2 rho, the vanishing
+    third- and fourth-order Hermite moments)."""
+    c_f, w_f, cs2 = orc.lattice(2)
+    c_s, w_s, _ = orc.lattice(0)
+    p = W.params(dim=2, nx=1, ny=1, nz=1, flow=1, xbc=0, collision=1, nu=0.05, omega_bulk=1.3)
+    tau = p["nu"] / cs2 + 0.5
+    om = 1 / tau
+    s = orc.Sim(p, init=False)
+    rng = np.random.default_rng(7)
+    for trial in range(10):
+        phi = rng.uniform(-0.95, 0.95)
+        s.h[:] = (w_s * phi)[:, None, None, None]
+        s.g[:] = (w_s * 0.1)[:, None, None, None]
+        s.phi_prev[:] = phi
+        s.f[:] = (w_f * (1 + rng.normal(size=9) * 0.08))[:, None, None, None]
+        f0 = s.f[:, 0, 0, 0].copy()
+        rho, m = f0.sum(), (c_f * f0[:, None]).sum(0)
+        K = p["h_drag"] * tau * (1 + phi) ** 2 * (1 - phi) / (4 * p["W0"] ** 2)
+        u = m / (rho + K / 2)
+        F = -K * u
+        us = (1 - phi) / 2 * u
+        xi = c_f[:, :2] - us[:2]
+        k = lambda a, b: (f0 * xi[:, 0] ** a * xi[:, 1] ** b).sum()  # central monomial moments
+        Hxx, Hyy, Hxy = k(2, 0) - rho * cs2, k(0, 2) - rho * cs2, k(1, 1)
+        t = (Hxx + Hyy) / 2
+        Ks = np.zeros((3, 3))
+        Ks[0, 0] = rho
+        Ks[1, 0] = (1 - om) * k(1, 0) + (1 - om / 2) * F[0]
+        Ks[0, 1] = (1 - om) * k(0, 1) + (1 - om / 2) * F[1]
+        Ks[2, 0] = (1 - om) * (Hxx - t) + (1 - p["omega_bulk"]) * t + rho * cs2
+        Ks[0, 2] = (1 - om) * (Hyy - t) + (1 - p["omega_bulk"]) * t + rho * cs2
+        Ks[1, 1] = (1 - om) * Hxy
+        Ks[2, 1], Ks[1, 2] = cs2 * Ks[0, 1], cs2 * Ks[1, 0]
+        Ks[2, 2] = cs2 * (Ks[2, 0] + Ks[0, 2]) - cs2 ** 2 * rho
+        v = np.array([-1.0, 0.0, 1.0])
+        Tx = np.linalg.inv(np.array([(v - us[0]) ** n for n in range(3)]))
+        Ty = np.linalg.inv(np.array([(v - us[1]) ** n for n in range(3)]))
+        g = Tx @ Ks @ Ty.T  # g[i, j]: population with velocity (v[i], v[j])
+        s.step(1)
+        f1 = s.f[:, 0, 0, 0]
+        for a in range(9):
+            i, j = int(c_f[a, 0]) + 1, int(c_f[a, 1]) + 1
+            assert abs(f1[a] - g[i, j]) < 1e-15
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_chmrt_shear_wave_decay_and_fixed_point(orc, dim):
+    """The shear viscosity is cs2 (tau_f - 1/2) whatever the bulk rate; a uniform flow is a fixed
+    point after its first step (which only sets the higher central moments to equilibrium)."""
+    ny = 64
+    p = W.params(dim=dim, nx=4, ny=ny, nz=1 if dim == 2 else 4, flow=1, seed_R=-1e9, collision=1,
+                 omega_bulk=1.4)
+    s = orc.Sim(p, init=False)
+    w = scalar_weights(dim)
+    s.h[:] = -w[:, None, None, None]
+    s.g[:] = (0.1 * w)[:, None, None, None]
+    s.phi_prev[:] = -1.0
+    k = 2 * math.pi / ny
+    y = np.arange(ny)
+    ux = np.broadcast_to((1e-3 * np.sin(k * y))[None, :, None], s.shape)
+    s.set_flow_equilibrium(1.0, ux, 0.0, 0.0)
+
+    def amp():
+        return (s.fields()["ux"][0, :, 0] * np.sin(k * y)).sum() * 2 / ny
+
+    s.step(100)
+    a0 = amp()
+    s.step(1000)
+    a1 = amp()
+    nu_meas = -math.log(a1 / a0) / (1000 * k * k)
+    assert abs(nu_meas / p["nu"] - 1) < 5e-3
+
+    s = orc.Sim(p, init=False)
+    s.h[:] = -w[:, None, None, None]
+    s.g[:] = (0.1 * w)[:, None, None, None]
+    s.phi_prev[:] = -1.0
+    s.set_flow_equilibrium(1.0, 0.06, -0.03, 0.02 if dim == 3 else 0.0)
+    s.step(1)
+    f1, fl = s.f.copy(), s.fields()
+    assert np.abs(fl["rho"] - 1).max() < 1e-15 and np.abs(fl["ux"] - 0.06).max() < 1e-15
+    s.step(1)
+    assert np.abs(s.f - f1).max() < 1e-16
+
+
+def test_chmrt_keeps_a_low_viscosity_shear_layer_stable(orc):
+    """The reason for the collision: a doubly periodic shear layer at nu = 1e-5 diverges with BGK
+    within 1000 steps and stays bounded with the central-Hermite MRT."""
+    n, u0 = 64, 0.05
+    x = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(x, x)
+    ux = np.where(Y <= 0.5, u0 * np.tanh(80 * (Y - 0.25)), u0 * np.tanh(80 * (0.75 - Y)))
+    uy = 0.05 * u0 * np.sin(2 * np.pi * (X + 0.25))
+    umax = {}
+    for coll in (0, 1):
+        p = W.params(dim=2, nx=n, ny=n, flow=1, seed_R=-1e9, nu=1e-5, collision=coll)
+        s = orc.Sim(p, init=False)
+        w = scalar_weights(2)
+        s.h[:] = -w[:, None, None, None]
+        s.g[:] = (0.1 * w)[:, None, None, None]
+        s.phi_prev[:] = -1.0
+        s.set_flow_equilibrium(1.0, ux[None], uy[None], 0.0)
+        with np.errstate(invalid="ignore", over="ignore"):
+            s.step(1500)
+            umax[coll] = float(np.abs(s.fields()["ux"]).max())
+    assert not np.isfinite(umax[0]) or umax[0] > 1.0
+    assert np.isfinite(umax[1]) and umax[1] < 2 * u0
+
+
 def test_walls_conserve_solute_and_mass(orc):
     """A box closed by wall rows (zero flux for U, no-slip for f): the solute-plus-solid invariant
     and the fluid mass stay exact while a seed grows and a shear flow decays against the walls."""
