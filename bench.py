@@ -213,9 +213,11 @@ def _kernel_tag(name: str) -> str:
     """Short tag of a demangled kernel name."""
     if "step_single<" in name:
         args = name.split("step_single<", 1)[1].split(">", 1)[0].replace(" ", "")
-        dim, flow, real, fst = args.split(",")[:4]
+        parts = args.split(",")
+        dim, flow, real, fst = parts[:4]
         prec = {"double": "fp64", "float": "fp32", "__half": "fp16shift"}[fst]
-        return f"step_{dim}d_{'flow' if flow == 'true' else 'noflow'}_{prec}"
+        extra = "".join(f"_{k}" for k, i in (("walls", 10), ("chmrt", 11)) if len(parts) > i and parts[i] == "true")
+        return f"step_{dim}d_{'flow' if flow == 'true' else 'noflow'}{extra}_{prec}"
     if "copyBuffer" in name:
         return "copy_1GiB"
     return name.split("(")[0].split("<")[0].replace("void ", "").strip()
@@ -375,6 +377,8 @@ def main():
         s.step(20)
         s16 = lbcg.Solver(W.config3(), "fp16shift")
         s16.step(20)
+        sm = lbcg.Solver(dict(W.config3(), collision=1, omega_bulk=1.0), "fp32")
+        sm.step(20)
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(5):
@@ -388,6 +392,8 @@ def main():
     c2 = gpu_case("3-D no-flow 128^3 fp32", W.config2(), "fp32", args.steps, args.warmup, False)
     pw, mw = W.config3_walls()
     c3w = gpu_case("3-D flow 192x128x128 fp32, walls and a baffle", pw, "fp32", args.steps, args.warmup, False, mw)
+    chm = gpu_case("3-D flow 192x128x128 fp32, central-Hermite MRT", dict(p3, collision=1, omega_bulk=1.0), "fp32",
+                   args.steps, args.warmup, False)
     sweep = None if args.no_sweep else sweep_case(args.sweep_n, args.sweep_steps, MEASURE_EVERY)
     surr = None
     if not args.no_surrogate:
@@ -429,6 +435,7 @@ def main():
             "fp16shift_flow": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in f16.items()},
             "no_flow_128cube": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c2.items()},
             "flow_walls_baffle": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c3w.items()},
+            "flow_chmrt": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in chm.items()},
         },
     }
     print(json.dumps(rec), flush=True)

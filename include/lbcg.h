@@ -99,9 +99,20 @@ typedef struct {
     double grad_eps2;    /* |grad phi|^2 at or below which a_s = 1 and the anisotropy flux is 0 */
     int32_t seed_shape;  /* lbcg_seed_shape; polygons have circumradius seed_radius and are prisms
                           * of half-height equal to their apothem in 3-D */
-    int32_t reserved;    /* must be 0 */
+    int32_t collision;   /* lbcg_collision of the flow populations (0 without flow) */
     double seed_tilt;    /* rotation of a polygonal seed about z, radians (the paper's seed tilt) */
+    double omega_bulk;   /* central-Hermite MRT only: relaxation rate of the trace of the second-order
+                          * central moment, in (0, 2) (1: to equilibrium in one step) */
 } lbcg_params;
+
+/* Flow collision (Section 2.2, flow paragraph: BGK, or the central-Hermite multiple-relaxation-time
+ * operator the paper names for stability). The MRT works on central Hermite moments about u*
+ * (He0 = 1, He1 = xi, He2 = xi^2 - cs^2 per direction; on D2Q9 the multi-indices with n_x, n_y <= 2,
+ * on D3Q19 the 19 with each n_d <= 2 and at most two non-zero): rho kept; first order to
+ * (1 - w) k + (1 - w/2) F, the BGK-Guo momentum update; the deviatoric second order relaxes with
+ * w = 1/tau_f and its trace with omega_bulk; third and fourth orders to zero. Needs flow = 1; the
+ * z-marching tiling does not implement it. */
+typedef enum { LBCG_COLLISION_BGK = 0, LBCG_COLLISION_CHMRT = 1 } lbcg_collision;
 
 /* Seed shapes (Section 4: rhombic and hexagonal seeds, tilted). The initial phase field is
  * phi0 = tanh(-d / (sqrt(2) W0)) with d the signed distance to the seed: |x - c| - R for the

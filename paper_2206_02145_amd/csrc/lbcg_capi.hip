@@ -79,13 +79,16 @@ void validate(const lbcg_params* p) {
     if (p->xbc != LBCG_PERIODIC && p->nx < 3) throw Error(LBCG_EINVAL, "open x faces need nx >= 3");
     if (p->walls != 0 && p->walls != 1) throw Error(LBCG_EINVAL, "walls must be 0 or 1");
     if (p->seed_shape < LBCG_SEED_CIRCLE || p->seed_shape > LBCG_SEED_RHOMBUS) throw Error(LBCG_EINVAL, "unknown seed shape");
-    if (p->reserved != 0) throw Error(LBCG_EINVAL, "reserved must be 0");
+    if (p->collision != LBCG_COLLISION_BGK && p->collision != LBCG_COLLISION_CHMRT)
+        throw Error(LBCG_EINVAL, "unknown collision");
+    if (p->collision == LBCG_COLLISION_CHMRT && !p->flow)
+        throw Error(LBCG_EINVAL, "the central-Hermite MRT collision applies to the flow populations (flow = 1)");
     const double N = (double)p->nx * p->ny * p->nz;
     if (N >= 536870912.0)  // each population plane is addressed with 32-bit byte offsets
         throw Error(LBCG_EINVAL, "grid too large (at most 2^29 - 1 nodes)");
     const double vals[] = {p->W0, p->tau0, p->lambda, p->D, p->eps_aniso, p->nu, p->h_drag,
                            p->u_inlet, p->U0, p->U_inlet, p->seed_center[0], p->seed_center[1],
-                           p->seed_center[2], p->seed_radius, p->grad_eps2, p->seed_tilt};
+                           p->seed_center[2], p->seed_radius, p->grad_eps2, p->seed_tilt, p->omega_bulk};
     for (double v : vals)
         if (!std::isfinite(v)) throw Error(LBCG_EINVAL, "non-finite parameter");
     if (!(p->tau0 > 0) || !(p->W0 > 0))
@@ -95,6 +98,8 @@ void validate(const lbcg_params* p) {
     if (!(p->D >= 0)) throw Error(LBCG_EUNSTABLE, "D must be >= 0 (tau_U >= 1/2)");
     if (p->flow && !(p->nu > 0)) throw Error(LBCG_EUNSTABLE, "nu must be > 0 (tau_f > 1/2)");
     if (!(p->grad_eps2 >= 0)) throw Error(LBCG_EINVAL, "grad_eps2 must be >= 0");
+    if (p->collision == LBCG_COLLISION_CHMRT && !(p->omega_bulk > 0 && p->omega_bulk < 2))
+        throw Error(LBCG_EUNSTABLE, "omega_bulk must lie in (0, 2)");
 }
 
 struct Layout {
@@ -133,6 +138,7 @@ struct Tiling {
     int laux = 0;   // cache policy of the single-use loads (g, f, phi_prev)
     int zband = 0;  // z tile-layers per band of the block tile order (0: plain x, y, z order)
     bool walls = false;  // the kernel honours the solid-wall mask
+    bool chm = false;    // central-Hermite MRT flow collision
 };
 
 InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling& T) {
@@ -180,7 +186,8 @@ InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling&
     I.kd[K_UIN] = I.u_in;
     I.kd[K_DQ] = I.D * inv_cs2;
     I.kd[K_UIN2] = 2.0 * (I.U_in - I.U0);
-    for (int k = 0; k < 12; k++) I.kf[k] = (float)I.kd[k];
+    I.kd[K_OMB] = p->collision == LBCG_COLLISION_CHMRT ? p->omega_bulk : 1.0;
+    for (int k = 0; k < 16; k++) I.kf[k] = (float)I.kd[k];
     return I;
 }
 
@@ -252,17 +259,18 @@ struct CommonOps {
 };
 
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
-          int LAUX = 0, bool WALLS = false>
+          int LAUX = 0, bool WALLS = false, bool CHM = false>
 struct BlockOps : CommonOps<DIM, FLOW, real, fst> {
     using C = CommonOps<DIM, FLOW, real, fst>;
     static void step(const InstDev& I, int par, hipStream_t s) {
         const int nblocks = I.tiles_x * I.tiles_y * I.tiles_z;
-        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS>), dim3(nblocks),
+        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM>), dim3(nblocks),
                            dim3(TX * TY * TZ), 0, s, I, par);
     }
     static Ops ops() {
         Tiling t{false, TX, TY, TZ, PF, AUX, LAUX, 0};
         t.walls = WALLS;
+        t.chm = CHM;
         return Ops{t, step, C::init, C::field, C::reduce, C::ray};
     }
 };
@@ -372,8 +380,45 @@ std::vector<Variant> wall_variants(bool large) {
     return v;
 }
 
+// Tilings of the central-Hermite MRT flow kernel, with or without walls (the first is the default).
+template <int DIM, typename real, typename fst>
+std::vector<Variant> chm_variants(bool large, bool walls) {
+    std::vector<Variant> v;
+    auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
+    if constexpr (DIM == 2) {
+        static const Ops a = BlockOps<2, true, real, fst, 64, 4, 1, false, 0, 0, false, true>::ops();
+        static const Ops b = BlockOps<2, true, real, fst, 64, 4, 1, false, 2, 0, false, true>::ops();
+        static const Ops w = BlockOps<2, true, real, fst, 64, 4, 1, false, 0, 0, true, true>::ops();
+        if (walls) add(w);
+        else if (large || sizeof(real) == 8) {
+            add(b);
+            add(a);
+        } else {
+            add(a);
+            add(b);
+        }
+    } else if constexpr (sizeof(real) == 8) {
+        static const Ops a = BlockOps<3, true, real, fst, 16, 4, 4, false, 0, 0, false, true>::ops();
+        static const Ops w = BlockOps<3, true, real, fst, 16, 4, 4, false, 0, 0, true, true>::ops();
+        add(walls ? w : a);
+    } else {
+        static const Ops a0 = BlockOps<3, true, real, fst, 64, 2, 4, false, 0, 0, false, true>::ops();
+        static const Ops a2 = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 0, false, true>::ops();
+        static const Ops a3 = BlockOps<3, true, real, fst, 64, 2, 4, true, 2, 0, false, true>::ops();
+        static const Ops w = BlockOps<3, true, real, fst, 64, 2, 4, false, 0, 0, true, true>::ops();
+        if (walls) add(w);
+        else if (large && std::is_same<fst, __half>::value) for (const Ops* o : {&a3, &a2, &a0}) add(*o);
+        else if (large) for (const Ops* o : {&a2, &a3, &a0}) add(*o);
+        else for (const Ops* o : {&a0, &a2, &a3}) add(*o);
+    }
+    return v;
+}
+
 template <int DIM, bool FLOW, typename real, typename fst>
-std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls) {
+std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls, bool chm) {
+    if constexpr (FLOW) {
+        if (chm) return chm_variants<DIM, real, fst>(pop_bytes > LLC_BYTES, walls);
+    }
     if (walls) return wall_variants<DIM, FLOW, real, fst>(pop_bytes > LLC_BYTES);
     std::vector<Variant> v;
     block_variants<DIM, FLOW, real, fst>(v, pop_bytes > LLC_BYTES);
@@ -401,18 +446,18 @@ std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls) {
 }
 
 // Candidate tilings for one grid kind; the first is the default. pop_bytes: both population copies.
-std::vector<Variant> variants_for(int dim, int flow, int prec, int nx, double pop_bytes, bool walls) {
+std::vector<Variant> variants_for(int dim, int flow, int prec, int nx, double pop_bytes, bool walls, bool chm) {
     const double b = pop_bytes;
     if (dim == 2) {
-        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx, b, walls) : variants_of<2, false, float, float>(nx, b, walls);
-        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx, b, walls)
-               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx, b, walls)
-                                   : variants_of<2, true, float, __half>(nx, b, walls);
+        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx, b, walls, false) : variants_of<2, false, float, float>(nx, b, walls, false);
+        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx, b, walls, chm)
+               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx, b, walls, chm)
+                                   : variants_of<2, true, float, __half>(nx, b, walls, chm);
     }
-    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx, b, walls) : variants_of<3, false, float, float>(nx, b, walls);
-    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx, b, walls)
-           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx, b, walls)
-                               : variants_of<3, true, float, __half>(nx, b, walls);
+    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx, b, walls, false) : variants_of<3, false, float, float>(nx, b, walls, false);
+    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx, b, walls, chm)
+           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx, b, walls, chm)
+                               : variants_of<3, true, float, __half>(nx, b, walls, chm);
 }
 
 double population_bytes(const lbcg_params& p) {
@@ -430,6 +475,7 @@ std::string variant_name(const Variant& v) {
                       t.aux ? " nt-stores" : "", t.laux ? " nt-loads" : "");
         if (t.zband > 1) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " zband %d", t.zband);
         if (t.walls) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " walls");
+        if (t.chm) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " chmrt");
     return buf;
 }
 
@@ -478,32 +524,43 @@ struct BatchKit {
                 double* out, hipStream_t);
 };
 
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX>
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, bool CHM = false>
 struct BatchImpl {
     static void step(const InstDev* d, int n, int tiles, int par, hipStream_t s) {
-        hipLaunchKernelGGL((step_batch<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX>), dim3(tiles), dim3(TX * TY * TZ),
-                           0, s, d, n, par);
+        hipLaunchKernelGGL((step_batch<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, 0, CHM>), dim3(tiles),
+                           dim3(TX * TY * TZ), 0, s, d, n, par);
     }
     static void ray(const InstDev* d, int n, int par, const double* dirs, int ndirs, const double* centers,
                     double* out, hipStream_t s) {
         hipLaunchKernelGGL((raymarch_batch_kernel<DIM, real>), dim3(ndirs, n), dim3(64), 0, s, d, par, dirs, ndirs,
                            centers, out);
     }
-    static BatchKit kit() { return BatchKit{Tiling{false, TX, TY, TZ, PF, AUX, 0, 0}, step, ray}; }
+    static BatchKit kit() {
+        Tiling t{false, TX, TY, TZ, PF, AUX, 0, 0};
+        t.chm = CHM;
+        return BatchKit{t, step, ray};
+    }
 };
 
-const BatchKit& batch_kit_for(int dim, int flow, int prec) {
-    static const BatchKit k2[2][3] = {
+// kind: 0 no flow, 1 BGK flow, 2 central-Hermite MRT flow
+const BatchKit& batch_kit_for(int dim, int kind, int prec) {
+    static const BatchKit k2[3][3] = {
         {BatchImpl<2, false, double, double, 64, 4, 1, false, 0>::kit(), BatchImpl<2, false, float, float, 64, 4, 1, false, 2>::kit(),
          BatchImpl<2, false, float, float, 64, 4, 1, false, 2>::kit()},
         {BatchImpl<2, true, double, double, 64, 4, 1, false, 0>::kit(), BatchImpl<2, true, float, float, 64, 4, 1, false, 2>::kit(),
-         BatchImpl<2, true, float, __half, 64, 4, 1, false, 2>::kit()}};
-    static const BatchKit k3[2][3] = {
+         BatchImpl<2, true, float, __half, 64, 4, 1, false, 2>::kit()},
+        {BatchImpl<2, true, double, double, 64, 4, 1, false, 0, true>::kit(),
+         BatchImpl<2, true, float, float, 64, 4, 1, false, 2, true>::kit(),
+         BatchImpl<2, true, float, __half, 64, 4, 1, false, 2, true>::kit()}};
+    static const BatchKit k3[3][3] = {
         {BatchImpl<3, false, double, double, 16, 4, 4, false, 0>::kit(), BatchImpl<3, false, float, float, 64, 2, 4, false, 2>::kit(),
          BatchImpl<3, false, float, float, 64, 2, 4, false, 2>::kit()},
         {BatchImpl<3, true, double, double, 16, 4, 4, false, 0>::kit(), BatchImpl<3, true, float, float, 64, 2, 4, false, 2>::kit(),
-         BatchImpl<3, true, float, __half, 64, 2, 4, false, 2>::kit()}};
-    return dim == 2 ? k2[flow][prec] : k3[flow][prec];
+         BatchImpl<3, true, float, __half, 64, 2, 4, false, 2>::kit()},
+        {BatchImpl<3, true, double, double, 16, 4, 4, false, 0, true>::kit(),
+         BatchImpl<3, true, float, float, 64, 2, 4, false, 2, true>::kit(),
+         BatchImpl<3, true, float, __half, 64, 2, 4, false, 2, true>::kit()}};
+    return dim == 2 ? k2[kind][prec] : k3[kind][prec];
 }
 
 // Per-instance population buffers inside a batch workspace (the single-grid layout without its
@@ -556,8 +613,9 @@ void validate_batch(int n, const lbcg_params* p) {
     long long tiles = 0;
     for (int i = 0; i < n; i++) {
         validate(&p[i]);
-        if (p[i].dim != p[0].dim || p[i].flow != p[0].flow || p[i].precision != p[0].precision)
-            throw Error(LBCG_EINVAL, "all instances of a batch need the same dim, flow and precision");
+        if (p[i].dim != p[0].dim || p[i].flow != p[0].flow || p[i].precision != p[0].precision ||
+            p[i].collision != p[0].collision)
+            throw Error(LBCG_EINVAL, "all instances of a batch need the same dim, flow, precision and collision");
         if (p[i].walls) throw Error(LBCG_EINVAL, "batches do not take walls");
         tiles += (long long)p[i].nx * p[i].ny * p[i].nz;
     }
@@ -631,8 +689,10 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
         hdl->L = L;
         hdl->ws = (char*)dev_workspace;
         hdl->stream = (hipStream_t)hip_stream;
-        hdl->variants = variants_for(p->dim, p->flow, p->precision, p->xbc == LBCG_INFLOW_PRESSURE ? 0 : p->nx,
-                                     population_bytes(*p), p->walls != 0);  // (nx 0: no z-marching tiling)
+        const bool chm = p->collision == LBCG_COLLISION_CHMRT;
+        hdl->variants = variants_for(p->dim, p->flow, p->precision,
+                                     (p->xbc == LBCG_INFLOW_PRESSURE || chm) ? 0 : p->nx,  // (0: no z-marching tiling)
+                                     population_bytes(*p), p->walls != 0, chm);
         hdl->variant = 0;
         hdl->ops = hdl->variants[0].ops;
         hdl->inst = make_inst(p, hdl->ws, L, hdl->variants[0].tiling);
@@ -986,6 +1046,8 @@ lbcg_status lbcg_set_walls(lbcg_handle* h, const uint8_t* mask, size_t bytes, in
     });
 }
 
+}  // extern "C"
+
 // ---- checkpoints ----
 
 namespace {
@@ -1016,6 +1078,8 @@ size_t state_bytes_of(const lbcg_handle* h) {
     return b;
 }
 }  // namespace
+
+extern "C" {
 
 size_t lbcg_state_bytes(const lbcg_handle* h) { return h ? state_bytes_of(h) : 0; }
 
@@ -1110,8 +1174,9 @@ lbcg_status lbcg_batch_create(int n, const lbcg_params* p, void* dev_workspace, 
         b->L = L;
         b->ws = (char*)dev_workspace;
         b->stream = (hipStream_t)hip_stream;
-        b->kit = &batch_kit_for(p[0].dim, p[0].flow, p[0].precision);
-        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0, false)[0].ops;
+        const int kind = p[0].flow ? (p[0].collision == LBCG_COLLISION_CHMRT ? 2 : 1) : 0;
+        b->kit = &batch_kit_for(p[0].dim, kind, p[0].precision);
+        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0, false, false)[0].ops;
         b->par = 0;
         b->nstep = 0;
         int tiles = 0;

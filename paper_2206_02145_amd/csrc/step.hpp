@@ -40,6 +40,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include "chmrt.hpp"
 #include "lattice.hpp"
 #include "mem.hpp"
 
@@ -64,8 +65,8 @@ struct InstDev {
     double u_in, U_in, U0;
     // Constants of the fused step, derived once on the host in binary64 and rounded to binary32
     // (the kernel reads those of its precision); indices K_*.
-    double kd[12];
-    float kf[12];
+    double kd[16];
+    float kf[16];
 };
 
 enum : int {
@@ -81,6 +82,7 @@ enum : int {
     K_UIN,        // inlet velocity
     K_DQ,         // D / cs^2
     K_UIN2,       // 2 (U_in - U0), the anti-bounce-back term
+    K_OMB,        // trace relaxation rate of the central-Hermite MRT flow collision
 };
 template <typename real> __device__ __forceinline__ real kconst(const InstDev& I, int k) {
     if constexpr (sizeof(real) == 4) return I.kf[k];
@@ -126,7 +128,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 // order is x, then z, then y, so the tiles above and below run B * tiles_x apart instead of a whole
 // layer apart and the z-halo of h is still in L2 when it is read again.
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
-          int LAUX = 0, bool WALLS = false>
+          int LAUX = 0, bool WALLS = false, bool CHM = false>
 __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, const int par) {
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
@@ -417,7 +419,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         }
     }
 
-    // ---- flow: BGK + Guo forcing of the drag, u* in the equilibrium ----
+    // ---- flow: BGK + Guo forcing of the drag, u* in the equilibrium (or the central-Hermite MRT) ----
     real usx = 0, usy = 0, usz = 0;
     if constexpr (FLOW) {
         real drho = 0, mx = 0, my = 0, mz = 0;
@@ -444,17 +446,24 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         const real uinx = kconst<real>(I, K_UIN);
         real fk[V::Q];
         real fsum = 0;
+        if constexpr (CHM) {
+            chm_collide<DIM, V, real>(fv, drho, rho, mx, my, mz, usx, usy, usz, Fx, Fy, Fz, inv_tau_f, guo,
+                                      kconst<real>(I, K_OMB), fk);
 #pragma unroll
-        for (int a = 0; a < V::Q; a++) {
-            const int cx = V::c(a, 0), cy = V::c(a, 1), cz = V::c(a, 2);
-            const real wa = (real)V::w(a);
-            const real cu = (real)cx * usx + (real)cy * usy + (real)cz * usz;
-            const real cF = (real)cx * Fx + (real)cy * Fy + (real)cz * Fz;
-            // f_eq - w = w [rho - 1 + rho (cu/cs2 + cu^2/(2 cs2^2) - uu/(2 cs2))]
-            const real feq = wa * (drho + rho * ((real)3 * cu + (real)4.5 * cu * cu - (real)1.5 * uu));
-            const real Sa = wa * guo * ((real)3 * cF + (real)9 * cu * cF - (real)3 * uF);
-            fk[a] = fv[a] - (fv[a] - feq) * inv_tau_f + Sa;
-            if (a) fsum += fk[a];
+            for (int a = 1; a < V::Q; a++) fsum += fk[a];
+        } else {
+#pragma unroll
+            for (int a = 0; a < V::Q; a++) {
+                const int cx = V::c(a, 0), cy = V::c(a, 1), cz = V::c(a, 2);
+                const real wa = (real)V::w(a);
+                const real cu = (real)cx * usx + (real)cy * usy + (real)cz * usz;
+                const real cF = (real)cx * Fx + (real)cy * Fy + (real)cz * Fz;
+                // f_eq - w = w [rho - 1 + rho (cu/cs2 + cu^2/(2 cs2^2) - uu/(2 cs2))]
+                const real feq = wa * (drho + rho * ((real)3 * cu + (real)4.5 * cu * cu - (real)1.5 * uu));
+                const real Sa = wa * guo * ((real)3 * cF + (real)9 * cu * cF - (real)3 * uF);
+                fk[a] = fv[a] - (fv[a] - feq) * inv_tau_f + Sa;
+                if (a) fsum += fk[a];
+            }
         }
         fk[0] = drho - fsum;  // mass: the collision and the Guo term leave sum_a (f_a - w_a) = rho - 1
 #pragma unroll
@@ -538,14 +547,15 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
 }
 
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX,
-          bool WALLS = false>
+          bool WALLS = false, bool CHM = false>
 __global__ __launch_bounds__(TX* TY* TZ) void step_single(InstDev I, int par) {
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS>(I, xcd_tile(blockIdx.x, gridDim.x), par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM>(I, xcd_tile(blockIdx.x, gridDim.x), par);
 }
 
 // Batched launch: the tiles of all instances form one list; each workgroup finds its instance
 // by binary search over the tile offsets.
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX = 0>
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX = 0,
+          bool CHM = false>
 __global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restrict__ insts, int ninst,
                                                          int par) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -564,7 +574,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restri
     for (int k = 0; k < (int)(sizeof(InstDev) / 4); k++) w[k] = __builtin_amdgcn_readfirstlane(src[k]);
     InstDev I;
     __builtin_memcpy(&I, w, sizeof(InstDev));
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX>(I, t - I.tile_begin, par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, false, CHM>(I, t - I.tile_begin, par);
 }
 
 }  // namespace lbcg

@@ -33,7 +33,8 @@ class lbcg_params(ctypes.Structure):
         ("h_drag", ctypes.c_double), ("u_inlet", ctypes.c_double), ("U0", ctypes.c_double),
         ("U_inlet", ctypes.c_double), ("seed_center", ctypes.c_double * 3),
         ("seed_radius", ctypes.c_double), ("grad_eps2", ctypes.c_double),
-        ("seed_shape", ctypes.c_int32), ("reserved", ctypes.c_int32), ("seed_tilt", ctypes.c_double),
+        ("seed_shape", ctypes.c_int32), ("collision", ctypes.c_int32), ("seed_tilt", ctypes.c_double),
+        ("omega_bulk", ctypes.c_double),
     ]
 
 
@@ -133,6 +134,7 @@ def make_params(p: dict, precision: str = "fp32") -> lbcg_params:
         s.seed_center[d] = float(p["seed_c"][d])
     s.seed_radius, s.grad_eps2 = p["seed_R"], p["grad_eps2"]
     s.seed_shape, s.seed_tilt = int(p.get("seed_shape", 0)), float(p.get("seed_tilt", 0.0))
+    s.collision, s.omega_bulk = int(p.get("collision", 0)), float(p.get("omega_bulk", 1.0))
     return s
 
 
