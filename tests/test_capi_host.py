@@ -61,6 +61,11 @@ def create_status(p, prec="fp32", nbytes=None):
     (dict(D=-0.1), "EUNSTABLE"),
     (dict(flow=1, nu=0.0), "EUNSTABLE"),
     (dict(U0=float("nan")), "EINVAL"),
+    (dict(xbc=3), "EINVAL"),
+    (dict(flow=1, collision=2), "EINVAL"),
+    (dict(flow=0, collision=1), "EINVAL"),        # the MRT collision is a flow option
+    (dict(flow=1, collision=1, omega_bulk=2.0), "EUNSTABLE"),
+    (dict(flow=1, collision=1, omega_bulk=float("nan")), "EINVAL"),
 ])
 def test_create_rejects_bad_parameters(change, expect):
     p = W.params(**change)
@@ -98,3 +103,23 @@ def test_surrogate_threshold_calibration():
     assert threshold_from([0.01, 0.02], [0.2, 0.0], 0.05) == 0.0
     thr = threshold_from([0.01, 0.02, 0.02], [0.0, 0.0, 0.09], 0.05)
     assert 0.01 <= thr < 0.02                                # a tie with the miss is excluded
+
+
+def test_params_struct_layout_matches_the_header(tmp_path):
+    """The binding's ctypes mirror of lbcg_params has the header's size and field offsets (a C
+    program built with gcc against include/lbcg.h prints them)."""
+    import subprocess
+    names = [f[0] for f in lbcg.lbcg_params._fields_]
+    cname = {"lambda_": "lambda"}
+    src = ["#include <stddef.h>", "#include <stdio.h>", '#include "lbcg.h"', "int main(void) {",
+           '  printf("%zu\\n", sizeof(lbcg_params));']
+    src += [f'  printf("%zu\\n", offsetof(lbcg_params, {cname.get(n, n)}));' for n in names]
+    src += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(lbcg.lbcg_params)
+    for n, off in zip(names, vals[1:]):
+        assert getattr(lbcg.lbcg_params, n).offset == off, n
