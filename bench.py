@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MEASURE_EVERY = 100
+PROFILE_STEPS = 200  # steps per solver in the profiled run (the first, colder launches weigh little)
 
 
 def log(*a):
@@ -47,7 +48,7 @@ def bytes_per_lup(p: dict, prec: str) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("step.hpp", "lattice.hpp"):
+    for f in ("step.hpp", "lattice.hpp", "mem.hpp", "chmrt.hpp"):
         with open(os.path.join(ROOT, "paper_2206_02145_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -374,11 +375,11 @@ def main():
     p3 = W.config3()
     if args.profile_run:
         s = lbcg.Solver(p3, "fp32")
-        s.step(20)
+        s.step(PROFILE_STEPS)
         s16 = lbcg.Solver(W.config3(), "fp16shift")
-        s16.step(20)
+        s16.step(PROFILE_STEPS)
         sm = lbcg.Solver(dict(W.config3(), collision=1, omega_bulk=1.0), "fp32")
-        sm.step(20)
+        sm.step(PROFILE_STEPS)
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(5):

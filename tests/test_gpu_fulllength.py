@@ -128,5 +128,7 @@ def test_full_length_flow_fp64(lb):
     dL, dVs, dM = aggregates(s, z)
     print(f"[fulllength] c3 fp64 @{steps}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
           f"; aggregates: max |dL| {dL:.2e} cells, Vs {dVs:.2e}, M' {dM:.2e}", flush=True)
-    assert dL <= 0.1 and dVs <= 1e-4 and dM <= 1e-5
+    assert dL <= 1e-4 and dVs <= 1e-8 and dM <= 1e-8
+    for k, v in errs.items():  # measured 1.5e-3 (phi): rounding-order differences amplified ~20x per 2000 steps
+        assert v <= 1e-2, (k, v)
     s.close()
