@@ -29,7 +29,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MEASURE_EVERY = 100
-PROFILE_STEPS = 200  # steps per solver in the profiled run (the first, colder launches weigh little)
 
 
 def log(*a):
@@ -47,10 +46,15 @@ def bytes_per_lup(p: dict, prec: str) -> int:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the step kernel's code (its headers with the comments and blank space removed), so
+    that counter figures taken on other code are not reported."""
+    import re
     h = hashlib.sha256()
     for f in ("step.hpp", "lattice.hpp", "mem.hpp", "chmrt.hpp"):
-        with open(os.path.join(ROOT, "paper_2206_02145_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2206_02145_amd", "csrc", f)) as fh:
+            code = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        code = re.sub(r"//[^\n]*", "", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -206,7 +210,7 @@ def cpu_baseline(p, budget_s: float = 15.0):
     return out
 
 
-PROFILE_STEPS = 20
+PROFILE_STEPS = 200  # steps per solver in the profiled run (the first, colder launches weigh little)
 COPY_BYTES = 1 << 30
 
 

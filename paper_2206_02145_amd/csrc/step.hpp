@@ -16,7 +16,10 @@
 // Open x faces: the inlet (x = 0) bounces back the populations leaving through it (velocity
 // bounce-back for f, anti-bounce-back with U = U_in for g, plain bounce-back of Eq. (d) for h);
 // at the outlet (x = nx-1) the unknown incoming populations take the value streamed into
-// x = nx-2, which the push writes twice.
+// x = nx-2, which the push writes twice; with the pressure outlet (I.xpress) the flow populations
+// leaving through x = nx-1 come back instead by anti-bounce-back at rho = 1.
+// Flow collision: BGK with Guo forcing, or (CHM) the central-Hermite MRT of chmrt.hpp. Solid walls
+// (WALLS): a node mask staged in LDS with the halo; populations aimed at a wall bounce back.
 //
 // Storage: every population array holds its deviation from a fixed reference, which keeps the
 // low-order bits where the dynamics happens and is what the binary16 mode stores:
