@@ -29,6 +29,23 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_capi_demo(verbose: bool = False) -> str:
+    """Compile tests/capi_demo.c, a C program that uses the library through include/lbcg.h only
+    (gcc, linked against liblbcg.so and the HIP runtime for its own device allocation)."""
+    root = os.path.dirname(HERE)
+    src = os.path.join(root, "tests", "capi_demo.c")
+    exe = os.path.join(root, "tests", "capi_demo")
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", src, "-I", os.path.join(root, "include"),
+           "-I", os.path.join(rocm, "include"), "-D__HIP_PLATFORM_AMD__", "-L", HERE, "-llbcg",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath,$ORIGIN/../paper_2206_02145_amd",
+           "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", exe]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return exe
+
+
 if __name__ == "__main__":
     build(verbose=True)
     print(LIB)
