@@ -80,13 +80,10 @@ def time_steps(s, steps: int, measure_every: int = 0, dirs=None):
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(st)
-    done = 0
-    while done < steps:
-        n = min(measure_every, steps - done) if measure_every else steps
-        s.step(n)
-        done += n
-        if measure_every and done % measure_every == 0:
-            s.measure(dirs)  # synchronises; the event brackets it
+    if measure_every:
+        s.run(steps, measure_every, dirs)  # diagnostics on the stream, copied back once; synchronises
+    else:
+        s.step(steps)
     e1.record(st)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1)

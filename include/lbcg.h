@@ -168,6 +168,19 @@ lbcg_status lbcg_write_field(lbcg_handle* h, int field, const void* src, size_t 
 lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* L_out,
                          double* mass_out);
 
+/* A run with diagnostics, without host round trips (the measurement sequence of Section 4.1.2,
+ * sizes and sums every measure_every steps): enqueue nsteps steps and, after every
+ * measure_every of them, the lbcg_measure diagnostics, whose results stay on the device until the
+ * run (or each block of up to 4096 / (6 + ndirs) samples) is copied back in one transfer.
+ * Samples = nsteps / measure_every; mass_hist[samples][6] and L_hist[samples][ndirs] receive them
+ * (either may be NULL) and every sample is appended to the growth-rate history, as lbcg_measure
+ * does. Remaining steps (nsteps mod measure_every) are enqueued after the last sample.
+ * Synchronises. Returns ENONFINITE if a sample found a non-finite value; the run then stops after
+ * that block (outputs filled up to it). Errors: EINVAL (NULL handle, nsteps < 0,
+ * measure_every < 1, bad directions), ENONFINITE (as lbcg_step). */
+lbcg_status lbcg_run(lbcg_handle* h, int64_t nsteps, int64_t measure_every, int ndirs, const double* dirs,
+                     double* L_hist, double* mass_hist);
+
 /* Least-squares growth rate of every direction over the recorded history (Section 4.1.2:
  * linear fit of length against time), in cells per step: G_out[ndirs], R2_out[ndirs]
  * (R^2 = 1 - A_res/A_tot), and *G_avg_out, the slope of the mean length. Needs >= 2 samples

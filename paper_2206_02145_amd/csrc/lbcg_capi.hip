@@ -62,6 +62,7 @@ size_t fstore_size(int prec) { return prec == LBCG_FP64 ? 8 : (prec == LBCG_FP32
 
 constexpr int MAX_DIRS = 256;
 constexpr int RED_BLOCKS = 1024;
+constexpr int HIST_DOUBLES = 4096;  // on-device measurement history of lbcg_run (32 KB)
 
 // Validation shared by single and batched creation; throws Error.
 void validate(const lbcg_params* p) {
@@ -103,7 +104,7 @@ void validate(const lbcg_params* p) {
 }
 
 struct Layout {
-    size_t h[2], g[2], f[2], phi_prev, staging, partials, dirs, out, wall, total;  // wall: 0 = none
+    size_t h[2], g[2], f[2], phi_prev, staging, partials, dirs, out, hist, wall, total;  // wall: 0 = none
 };
 
 Layout layout_of(const lbcg_params* p) {
@@ -124,6 +125,7 @@ Layout layout_of(const lbcg_params* p) {
     L.partials = take((RED_BLOCKS + 1) * RED_VALUES * 8);  // block partials, then the final values
     L.dirs = take(MAX_DIRS * 3 * 8);
     L.out = take((RED_VALUES + MAX_DIRS) * 8);
+    L.hist = take(HIST_DOUBLES * 8);
     L.wall = p->walls ? take(N) : 0;
     L.total = off;
     return L;
@@ -197,7 +199,7 @@ struct Ops {
     void (*step)(const InstDev&, int par, hipStream_t);
     void (*init)(const InstDev&, int par, const SeedArgs&, hipStream_t);
     void (*field)(const InstDev&, int par, int field, void* out, int dtype, hipStream_t);
-    void (*reduce)(const InstDev&, int par, double* partials, int nblocks, hipStream_t);
+    void (*reduce)(const InstDev&, int par, double* partials, int nblocks, double* out, hipStream_t);
     void (*ray)(const InstDev&, int par, const double* dirs, int ndirs, const double* c, double* out,
                 hipStream_t);
 };
@@ -246,10 +248,10 @@ struct CommonOps {
             hipLaunchKernelGGL((field_kernel<DIM, FLOW, real, fst, float>), dim3(nb), dim3(256), 0, s, I, par,
                                field, (float*)out);
     }
-    static void reduce(const InstDev& I, int par, double* partials, int nblocks, hipStream_t s) {
+    static void reduce(const InstDev& I, int par, double* partials, int nblocks, double* out, hipStream_t s) {
         hipLaunchKernelGGL((reduce_kernel<DIM, FLOW, real, fst>), dim3(nblocks), dim3(RED_THREADS), 0, s, I,
                            par, partials);
-        hipLaunchKernelGGL(reduce_final, dim3(1), dim3(64), 0, s, partials, nblocks, partials + nblocks * RED_VALUES);
+        hipLaunchKernelGGL(reduce_final, dim3(1), dim3(64), 0, s, partials, nblocks, out);
     }
     static void ray(const InstDev& I, int par, const double* dirs, int ndirs, const double* c, double* out,
                     hipStream_t s) {
@@ -716,16 +718,49 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
     return LBCG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+void enqueue_steps(lbcg_handle* h, int64_t nsteps) {
+    for (int64_t n = 0; n < nsteps; n++) {
+        h->ops->step(h->inst, h->par, h->stream);
+        h->par ^= 1;
+    }
+    h->nstep += nsteps;
+}
+
+void check_dirs(const lbcg_handle* h, int ndirs, const double* dirs) {
+    if (ndirs < 0 || ndirs > MAX_DIRS) throw Error(LBCG_EINVAL, "ndirs must be in [0, 256]");
+    if (ndirs > 0 && !dirs) throw Error(LBCG_EINVAL, "dirs is required when ndirs > 0");
+    for (int k = 0; k < ndirs; k++) {
+        const double* d = dirs + 3 * k;
+        const double n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (!(std::fabs(n2 - 1.0) < 1e-6)) throw Error(LBCG_EINVAL, "directions must be unit vectors");
+        if (h->p.dim == 2 && d[2] != 0.0) throw Error(LBCG_EINVAL, "2-D directions need z = 0");
+    }
+}
+
+// Keep a measurement's extents in the growth-rate history (restarted when ndirs changes).
+void record_history(lbcg_handle* h, double t, int ndirs, const double* L) {
+    if (ndirs <= 0) return;
+    if (h->hist_ndirs != ndirs) {
+        h->hist_ndirs = ndirs;
+        h->hist_t.clear();
+        h->hist_L.clear();
+    }
+    h->hist_t.push_back(t);
+    h->hist_L.insert(h->hist_L.end(), L, L + ndirs);
+}
+}  // namespace
+
+extern "C" {
+
 lbcg_status lbcg_step(lbcg_handle* h, int64_t nsteps) {
     return guarded([&] {
         if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
         if (nsteps < 0) throw Error(LBCG_EINVAL, "nsteps must be >= 0");
         if (h->nonfinite) throw Error(LBCG_ENONFINITE, "the last measurement found a non-finite value");
-        for (int64_t n = 0; n < nsteps; n++) {
-            h->ops->step(h->inst, h->par, h->stream);
-            h->par ^= 1;
-        }
-        h->nstep += nsteps;
+        enqueue_steps(h, nsteps);
         HIPCHK(hipGetLastError());
     });
 }
@@ -830,18 +865,12 @@ lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* 
     bool nonfinite = false;
     lbcg_status st = guarded([&] {
         if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
-        if (ndirs < 0 || ndirs > MAX_DIRS) throw Error(LBCG_EINVAL, "ndirs must be in [0, 256]");
-        if (ndirs > 0 && (!dirs || !L_out)) throw Error(LBCG_EINVAL, "dirs and L_out are required");
-        for (int k = 0; k < ndirs; k++) {
-            const double* d = dirs + 3 * k;
-            const double n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            if (!(std::fabs(n2 - 1.0) < 1e-6)) throw Error(LBCG_EINVAL, "directions must be unit vectors");
-            if (h->p.dim == 2 && d[2] != 0.0) throw Error(LBCG_EINVAL, "2-D directions need z = 0");
-        }
+        check_dirs(h, ndirs, dirs);
+        if (ndirs > 0 && !L_out) throw Error(LBCG_EINVAL, "L_out is required when ndirs > 0");
         double* part = (double*)(h->ws + h->L.partials);
         double* ddirs = (double*)(h->ws + h->L.dirs);
         double* dout = (double*)(h->ws + h->L.out);
-        h->ops->reduce(h->inst, h->par, part, h->red_blocks, h->stream);
+        h->ops->reduce(h->inst, h->par, part, h->red_blocks, part + h->red_blocks * RED_VALUES, h->stream);
         HIPCHK(hipGetLastError());
         if (ndirs > 0) {
             HIPCHK(hipMemcpyAsync(ddirs, dirs, sizeof(double) * 3 * ndirs, hipMemcpyHostToDevice, h->stream));
@@ -857,19 +886,65 @@ lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* 
         HIPCHK(hipStreamSynchronize(h->stream));
         if (mass_out) std::memcpy(mass_out, host, sizeof(double) * RED_VALUES);
         if (ndirs > 0) std::memcpy(L_out, host + RED_VALUES, sizeof(double) * ndirs);
-        if (ndirs > 0) {
-            if (h->hist_ndirs != ndirs) {
-                h->hist_ndirs = ndirs;
-                h->hist_t.clear();
-                h->hist_L.clear();
-            }
-            h->hist_t.push_back((double)h->nstep);
-            h->hist_L.insert(h->hist_L.end(), host + RED_VALUES, host + RED_VALUES + ndirs);
-        }
+        record_history(h, (double)h->nstep, ndirs, host + RED_VALUES);
         if (host[5] > 0) {
             h->nonfinite = true;
             nonfinite = true;
         }
+    });
+    if (st == LBCG_OK && nonfinite) {
+        lbcg::last_error_slot() = "non-finite phi, U or rho found";
+        return LBCG_ENONFINITE;
+    }
+    return st;
+}
+
+lbcg_status lbcg_run(lbcg_handle* h, int64_t nsteps, int64_t measure_every, int ndirs, const double* dirs,
+                     double* L_hist, double* mass_hist) {
+    bool nonfinite = false;
+    lbcg_status st = guarded([&] {
+        if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
+        if (nsteps < 0) throw Error(LBCG_EINVAL, "nsteps must be >= 0");
+        if (measure_every < 1) throw Error(LBCG_EINVAL, "measure_every must be >= 1");
+        check_dirs(h, ndirs, dirs);
+        if (h->nonfinite) throw Error(LBCG_ENONFINITE, "the last measurement found a non-finite value");
+        const int per = RED_VALUES + ndirs;               // values per sample in the device history
+        const int64_t cap = HIST_DOUBLES / per;            // samples per round trip (>= 15)
+        const int64_t samples = nsteps / measure_every;
+        double* part = (double*)(h->ws + h->L.partials);
+        double* ddirs = (double*)(h->ws + h->L.dirs);
+        double* dhist = (double*)(h->ws + h->L.hist);
+        if (ndirs > 0)
+            HIPCHK(hipMemcpyAsync(ddirs, dirs, sizeof(double) * 3 * ndirs, hipMemcpyHostToDevice, h->stream));
+        std::vector<double> host((size_t)std::min<int64_t>(cap, std::max<int64_t>(samples, 1)) * per);
+        std::vector<double> tsample;
+        for (int64_t s0 = 0; s0 < samples && !nonfinite; s0 += cap) {
+            const int64_t k = std::min(cap, samples - s0);
+            tsample.clear();
+            for (int64_t j = 0; j < k; j++) {  // steps and measurements, all on the stream
+                enqueue_steps(h, measure_every);
+                tsample.push_back((double)h->nstep);
+                double* slot = dhist + j * per;
+                h->ops->reduce(h->inst, h->par, part, h->red_blocks, slot, h->stream);
+                if (ndirs > 0) h->ops->ray(h->inst, h->par, ddirs, ndirs, h->p.seed_center, slot + RED_VALUES, h->stream);
+            }
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(host.data(), dhist, sizeof(double) * k * per, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            for (int64_t j = 0; j < k; j++) {
+                const double* v = host.data() + j * per;
+                if (mass_hist) std::memcpy(mass_hist + (s0 + j) * RED_VALUES, v, sizeof(double) * RED_VALUES);
+                if (ndirs > 0 && L_hist) std::memcpy(L_hist + (s0 + j) * ndirs, v + RED_VALUES, sizeof(double) * ndirs);
+                record_history(h, tsample[j], ndirs, v + RED_VALUES);
+                if (v[5] > 0) nonfinite = true;
+            }
+        }
+        if (nonfinite) {
+            h->nonfinite = true;
+            return;
+        }
+        enqueue_steps(h, nsteps - samples * measure_every);
+        HIPCHK(hipGetLastError());
     });
     if (st == LBCG_OK && nonfinite) {
         lbcg::last_error_slot() = "non-finite phi, U or rho found";

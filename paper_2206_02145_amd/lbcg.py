@@ -67,6 +67,7 @@ def lib():
         L.lbcg_read_field.argtypes = [vp, i32, vp, sz, i32, i32]
         L.lbcg_write_field.argtypes = [vp, i32, vp, sz, i32, i32]
         L.lbcg_measure.argtypes = [vp, i32, dp, dp, dp]
+        L.lbcg_run.argtypes = [vp, i64, i64, i32, dp, dp, dp]
         L.lbcg_growth_rates.argtypes = [vp, dp, dp, dp]
         L.lbcg_destroy.argtypes = [vp]
         L.lbcg_set_walls.argtypes = [vp, vp, sz, i32]
@@ -247,6 +248,21 @@ class Solver:
             check(code, "lbcg_measure")
         mass = dict(sumU=m[0], sumPhiPrev=m[1], Vs=m[2], Mprime=m[3], umax=m[4], nonfinite=m[5])
         return L[:nd], mass
+
+    def run(self, nsteps: int, measure_every: int, dirs=None, raise_nonfinite: bool = True):
+        """nsteps steps with the diagnostics every measure_every steps, kept on the device and copied
+        back once (lbcg_run). Returns (L_hist [samples, ndirs], mass_hist [samples] of dicts)."""
+        dirs = np.zeros((0, 3)) if dirs is None else np.ascontiguousarray(dirs, dtype=np.float64)
+        nd = dirs.shape[0]
+        ns = int(nsteps) // int(measure_every)
+        L = np.zeros((max(ns, 1), max(nd, 1)))
+        M = np.zeros((max(ns, 1), 6))
+        code = lib().lbcg_run(self.handle, int(nsteps), int(measure_every), nd, _dptr(dirs) if nd else None,
+                              _dptr(L) if nd else None, _dptr(M))
+        if code != -5 or raise_nonfinite:
+            check(code, "lbcg_run")
+        keys = ("sumU", "sumPhiPrev", "Vs", "Mprime", "umax", "nonfinite")
+        return L[:ns, :nd], [dict(zip(keys, row)) for row in M[:ns]]
 
     def growth_rates(self, ndirs: int):
         G = np.zeros(ndirs)

@@ -39,7 +39,8 @@ def test_workspace_bytes(cfg, prec, qs, qf, rs, fs):
     n = cfg["nx"] * cfg["ny"] * cfg["nz"]
     b = lbcg.lbcg_workspace_bytes(lbcg.make_params(cfg, prec))
     core = 2 * qs * n * rs * 2 + 2 * qf * n * fs + n * rs  # ping-pong h, g, f and phi_prev
-    assert core + 8 * n <= b <= core + 8 * n + 64 * 1024
+    # plus staging (8 B a node), reduction partials, directions and the 32 KB measurement history
+    assert core + 8 * n <= b <= core + 8 * n + 128 * 1024
 
 
 def create_status(p, prec="fp32", nbytes=None):

@@ -210,6 +210,51 @@ def test_growth_rates_match_oracle_fit(lb, orc):
     s.close()
 
 
+@pytest.mark.parametrize("nsteps,every,ndirs", [(1050, 100, 16), (200, 5, 256)])
+def test_run_with_diagnostics_equals_step_and_measure(lb, nsteps, every, ndirs):
+    """lbcg_run (diagnostics kept on the device, one copy back per block of samples; 256 directions
+    make blocks of 15 samples) gives bit for bit what lbcg_step + lbcg_measure give, including the
+    growth-rate history and the steps after the last sample."""
+    p = W.params(dim=3, nx=40, ny=32, nz=32, flow=1, xbc=1, u_in=0.02, U0=0.3, U_in=0.3,
+                 seed_c=(16.0, 16.0, 16.0), seed_R=6.0)
+    dirs = W.directions(ndirs, 3)
+    a = lb.Solver(p, "fp32")
+    L_run, m_run = a.run(nsteps, every, dirs)
+    b = lb.Solver(p, "fp32")
+    L_seq, m_seq = [], []
+    for _ in range(nsteps // every):
+        b.step(every)
+        L, m = b.measure(dirs)
+        L_seq.append(L)
+        m_seq.append(m)
+    b.step(nsteps % every)
+    assert L_run.shape == (nsteps // every, ndirs) and a.nstep == b.nstep == nsteps
+    assert np.array_equal(L_run, np.array(L_seq))
+    for x, y in zip(m_run, m_seq):
+        assert all(x[k] == y[k] for k in ("sumU", "sumPhiPrev", "Vs", "Mprime", "umax", "nonfinite"))
+    if ndirs == 16:
+        assert all(np.array_equal(u, v) for u, v in zip(a.growth_rates(ndirs), b.growth_rates(ndirs)))
+    for k in ("raw_h", "raw_g", "raw_f", "phi_prev"):
+        assert np.array_equal(a.read(k), b.read(k)), k
+    a.close()
+    b.close()
+
+
+def test_run_reports_nonfinite(lb):
+    p = W.params(dim=2, nx=32, ny=32, seed_c=(16, 16, 0))
+    s = lb.Solver(p, "fp32")
+    h = s.read("raw_h")
+    h[0, 0, 3, 3] = np.nan
+    s.write("raw_h", h)
+    with pytest.raises(lb.LbcgError) as e:
+        s.run(50, 10, W.directions(4))
+    assert e.value.status == "ENONFINITE"
+    with pytest.raises(lb.LbcgError) as e:
+        s.step(1)
+    assert e.value.status == "ENONFINITE"
+    s.close()
+
+
 def test_solute_plus_solid_invariant_fp32(lb):
     p = W.scaled(W.config2(), 64, 64, 64, seed_R=8.0)
     s = lb.Solver(p, "fp32")
