@@ -24,7 +24,10 @@ def argv(p, prec, steps):
 
 
 def test_demo_is_built_and_validates_before_the_device():
-    assert os.path.exists(EXE), "build() compiles tests/capi_demo"
+    if not os.path.exists(EXE):  # build() compiles it; a fresh checkout may not have run build()
+        from paper_2206_02145_amd import build
+        build.build_capi_demo()
+    assert os.path.exists(EXE)
     r = subprocess.run([EXE], capture_output=True, text=True)
     assert r.returncode == 2 and "usage" in r.stderr
     r = subprocess.run(argv(W.params(dim=4), "fp64", 1), capture_output=True, text=True)
