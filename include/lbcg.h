@@ -126,12 +126,14 @@ typedef struct lbcg_handle lbcg_handle;
 typedef struct lbcg_batch lbcg_batch;
 
 /* Bytes of device workspace one solver needs (0 if the parameters are invalid). It holds two
- * copies (ping-pong) of each population array, phi_prev, and a staging area for read-back. */
+ * copies (ping-pong) of each population array, phi_prev, a staging area for read-back, the
+ * reduction scratch, the measurement history of lbcg_run (32 KB) and, with walls, the wall mask. */
 size_t lbcg_workspace_bytes(const lbcg_params* p);
 
 /* Validate p, bind the caller's workspace (device pointer, >= lbcg_workspace_bytes bytes,
  * 256-byte aligned) and stream, and enqueue the initial state: the seed
- * phi0 = tanh((R - |x - c|) / (sqrt(2) W0)), h = w phi0, g = w U0,
+ * phi0 = tanh(-d / (sqrt(2) W0)) with d the signed distance to the seed shape (lbcg_seed_shape;
+ * d = |x - c| - R for the circle / sphere), h = w phi0, g = w U0,
  * f = f_eq(rho = 1, u* = u_inlet (1 - phi0)/2 x^), phi_prev = phi0.
  * Errors: EINVAL (sizes, enums, NULL pointers), EUNSTABLE, ENOMEM (workspace too small),
  * EDEVICE. On error *out is NULL. */
