@@ -28,7 +28,8 @@
  *   bounce-back for f, anti-bounce-back Dirichlet for g, bounce-back for h; outlet: unknown
  *   populations copied from x = nx-2; R17 equilibrium initial populations; R23 gradient ghost at
  *   an open face = copy of the face node; R27 the h bounce-back at the inlet uses the old value of
- *   the slot it writes; R30 optional pressure outlet; R31 the central-Hermite MRT flow collision.
+ *   the slot it writes; R30 optional pressure outlet; R31 the central-Hermite MRT flow collision;
+ *   R32 the anisotropy turns with the crystal's orientation.
  *
  * Units: lattice units, delta_t = delta_r = 1. Layout: pop[a][z][y][x], x fastest.
  */
@@ -175,6 +176,18 @@ void orc_aniso(double eps, double grad_eps2, const double* p, double* a, double*
     double as = 1.0 + eps * P6;
     *a = as;
     for (int d = 0; d < 3; d++) N[d] = 2.0 * eps * as * m * (gradP[d] - 6.0 * P6 * n[d]);
+}
+
+/* The anisotropy of the crystal turned by its orientation seed_tilt about z (R32): a_s and N
+ * evaluated in the crystal's frame, a_s = 1 + eps cos(6 (theta - tilt)) in 2-D, N turned back. */
+static void crystal_aniso(const orc_params* P, const double* p, double* a, double* N) {
+    double c = cos(P->seed_tilt), s = sin(P->seed_tilt);
+    double q[3] = {c * p[0] + s * p[1], -s * p[0] + c * p[1], p[2]};
+    double Nq[3];
+    orc_aniso(P->eps, P->grad_eps2, q, a, Nq);
+    N[0] = c * Nq[0] - s * Nq[1];
+    N[1] = s * Nq[0] + c * Nq[1];
+    N[2] = Nq[2];
 }
 
 /* ------------------------------------------------------------------------------------------ */
@@ -498,7 +511,7 @@ static void collide_stream(const orc_params* P, const double* h, const double* g
             double phi = s->phi[i], U = s->U[i];
             double p[3] = {s->px[i], s->py[i], s->pz[i]};
             double as, Nv[3];
-            orc_aniso(P->eps, P->grad_eps2, p, &as, Nv);
+            crystal_aniso(P, p, &as, Nv);
             double a2 = as * as;
 
             /* Phase field, Eq. (d) with Eq. (e). */

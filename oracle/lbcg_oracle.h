@@ -35,7 +35,8 @@ typedef struct {
                                         * walls are frozen, populations aimed at them bounce back */
     int32_t seed_shape;                /* 0 circle / sphere, 1 hexagon, 2 rhombus (60/120 degrees);
                                         * polygons are prisms in 3-D (R29) */
-    double seed_tilt;                  /* rotation of a polygonal seed about z (radians) */
+    double seed_tilt;                  /* orientation of the crystal about z (radians): turns a
+                                        * polygonal seed and the anisotropy axes (R32) */
     int32_t collision;                 /* flow collision: 0 BGK, 1 central-Hermite MRT (R31) */
     double omega_bulk;                 /* MRT relaxation rate of the trace of the second-order
                                         * central moment, in (0, 2) */

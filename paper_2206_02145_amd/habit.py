@@ -5,7 +5,9 @@
 * the quality Q = max L_i / min L_i (the baffle study, Section 4.2), 1 for isotropic growth;
 * the aspect ratio: extent along the flow (x) over the extent across it (y),
   (L(+x) + L(-x)) / (L(+y) + L(-y)) (reading of the forced-convection study, whose figure is
-  missing).
+  missing);
+* the upstream ratio L(-x) / L(+x) with the flow along +x: how much faster the inflow-facing side
+  grows than the downstream one.
 """
 from __future__ import annotations
 
@@ -38,7 +40,8 @@ def aspect_ratio(Lxp: float, Lxm: float, Lyp: float, Lym: float) -> float:
 def from_extents(L10) -> dict:
     """Habit numbers from the ten extents along habit_directions()."""
     L = np.asarray(L10, dtype=float)
-    return dict(L=L[:6], L_avg=float(L[:6].mean()), Q=quality(L[:6]), aspect=aspect_ratio(*L[6:10]))
+    return dict(L=L[:6], L_avg=float(L[:6].mean()), Q=quality(L[:6]), aspect=aspect_ratio(*L[6:10]),
+                upstream=float(L[7] / L[6]))
 
 
 def measure(solver, tilt: float = 0.0) -> dict:

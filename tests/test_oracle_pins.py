@@ -896,11 +896,29 @@ def test_faceted_seed_geometry(orc):
     assert np.abs(prof - np.tanh(-(k - a) / (math.sqrt(2) * W.BASE["W0"]))).max() < 1e-14
 
 
+def test_tilted_crystal_is_the_rotated_crystal(orc):
+    """The orientation turns the seed and the anisotropy together (R32): on a periodic square grid
+    without flow, a hexagonal crystal tilted by pi/2 grows into the field of the untilted one turned
+    by 90 degrees (the lattices are symmetric under that turn). Were only the seed turned, the
+    anisotropy 1 + eps cos(6 theta) would become 1 - eps cos(6 theta) relative to the crystal."""
+    n = 64
+    out = {}
+    for tilt in (0.0, math.pi / 2):
+        p = W.params(dim=2, nx=n, ny=n, U0=0.3, U_in=0.3, seed_c=((n - 1) / 2, (n - 1) / 2, 0.0), seed_R=10.0,
+                     seed_shape=1, seed_tilt=tilt)
+        s = orc.Sim(p)
+        s.step(400)
+        out[tilt] = s.fields()["phi"][0]
+    turned = np.rot90(out[0.0], k=-1)  # (x, y) -> (-y, x) about the grid centre; arrays are [y][x]
+    assert np.abs(out[math.pi / 2] - turned).max() < 1e-12
+    assert np.abs(out[0.0] - turned).max() > 1e-2  # the turn is not a symmetry of the hexagon
+
+
 def test_habit_numbers():
     from paper_2206_02145_amd import habit as H
     d = H.habit_directions(0.3)
     assert d.shape == (10, 3) and np.allclose(np.linalg.norm(d, axis=1), 1)
     assert np.allclose(np.degrees(np.arctan2(d[:6, 1], d[:6, 0])) % 360, (np.degrees(0.3) + 30 + 60 * np.arange(6)) % 360)
     h = H.from_extents([2, 3, 4, 4, 3, 2, 10, 6, 4, 4])
-    assert h["Q"] == 2.0 and h["aspect"] == 2.0 and h["L_avg"] == 3.0
+    assert h["Q"] == 2.0 and h["aspect"] == 2.0 and h["L_avg"] == 3.0 and h["upstream"] == 0.6
 
