@@ -100,7 +100,8 @@ typedef struct {
     int32_t seed_shape;  /* lbcg_seed_shape; polygons have circumradius seed_radius and are prisms
                           * of half-height equal to their apothem in 3-D */
     int32_t collision;   /* lbcg_collision of the flow populations (0 without flow) */
-    double seed_tilt;    /* rotation of a polygonal seed about z, radians (the paper's seed tilt) */
+    double seed_tilt;    /* orientation of the crystal about z, radians (the paper's seed tilt): turns
+                          * a polygonal seed and the anisotropy, a_s = 1 + eps cos 6(theta - tilt) */
     double omega_bulk;   /* central-Hermite MRT only: relaxation rate of the trace of the second-order
                           * central moment, in (0, 2) (1: to equilibrium in one step) */
 } lbcg_params;

@@ -189,6 +189,8 @@ InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling&
     I.kd[K_DQ] = I.D * inv_cs2;
     I.kd[K_UIN2] = 2.0 * (I.U_in - I.U0);
     I.kd[K_OMB] = p->collision == LBCG_COLLISION_CHMRT ? p->omega_bulk : 1.0;
+    I.kd[K_CT] = p->seed_tilt == 0.0 ? 1.0 : std::cos(p->seed_tilt);
+    I.kd[K_ST] = p->seed_tilt == 0.0 ? 0.0 : std::sin(p->seed_tilt);
     for (int k = 0; k < 16; k++) I.kf[k] = (float)I.kd[k];
     return I;
 }

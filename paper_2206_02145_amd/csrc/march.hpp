@@ -129,6 +129,7 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
     const real kc = (real)(I.k * S::inv_cs2);
     const real eps = (real)I.eps;
     const real geps2 = (real)I.grad_eps2;
+    const real ct = kconst<real>(I, K_CT), st = kconst<real>(I, K_ST);
     const real lam = (real)I.lambda, itau0 = (real)I.inv_tau0;
     const real DU = (real)(I.D * S::inv_cs2);
     const real U0 = (real)I.U0;
@@ -188,18 +189,20 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
             }
             real as = 1, Nx = 0, Ny = 0, Nz = 0;
             const real s2 = px * px + py * py + pz * pz;
-            if (s2 > geps2) {
+            if (s2 > geps2) {  // in the frame of the crystal turned by its orientation
                 const real m = sqrt(s2);
                 const real im = (real)1 / m;
-                const real ux_ = px * im, uy_ = py * im, uz_ = pz * im;
+                const real ux_ = (ct * px + st * py) * im, uy_ = (ct * py - st * px) * im, uz_ = pz * im;
                 const real z2r = ux_ * ux_ - uy_ * uy_, z2i = (real)2 * ux_ * uy_;
                 const real z4r = z2r * z2r - z2i * z2i, z4i = (real)2 * z2r * z2i;
                 const real z5r = z4r * ux_ - z4i * uy_, z5i = z4r * uy_ + z4i * ux_;
                 const real P6 = z5r * ux_ - z5i * uy_;
                 as = (real)1 + eps * P6;
                 const real c2 = (real)2 * eps * as * m;
-                Nx = c2 * ((real)6 * z5r - (real)6 * P6 * ux_);
-                Ny = c2 * ((real)-6 * z5i - (real)6 * P6 * uy_);
+                const real nx_ = c2 * ((real)6 * z5r - (real)6 * P6 * ux_);
+                const real ny_ = c2 * ((real)-6 * z5i - (real)6 * P6 * uy_);
+                Nx = ct * nx_ - st * ny_;
+                Ny = st * nx_ + ct * ny_;
                 Nz = c2 * ((real)-6 * P6 * uz_);
             }
             const real a2 = as * as;

@@ -86,6 +86,8 @@ enum : int {
     K_DQ,         // D / cs^2
     K_UIN2,       // 2 (U_in - U0), the anti-bounce-back term
     K_OMB,        // trace relaxation rate of the central-Hermite MRT flow collision
+    K_CT,         // cos and sin of the crystal's orientation (the anisotropy's frame)
+    K_ST,
 };
 template <typename real> __device__ __forceinline__ real kconst(const InstDev& I, int k) {
     if constexpr (sizeof(real) == 4) return I.kf[k];
@@ -340,22 +342,26 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         if (DIM == 3 && V::c(b, 2)) pz += (real)V::c(b, 2) * wc * ph;
     }
 
-    // anisotropy a_s = 1 + eps Re((nx + i ny)^6) and its flux N = 2 eps a_s |p| (grad P - 6 P n)
+    // anisotropy a_s = 1 + eps Re((nx + i ny)^6) and its flux N = 2 eps a_s |p| (grad P - 6 P n),
+    // in the frame of the crystal turned by its orientation (n and N turned about z)
     const real eps = kconst<real>(I, K_EPS);
+    const real ct = kconst<real>(I, K_CT), st = kconst<real>(I, K_ST);
     real as = 1, Nx = 0, Ny = 0, Nz = 0;
     const real s2 = px * px + py * py + pz * pz;
     if (s2 > kconst<real>(I, K_GEPS2)) {
         const real m = sqrt(s2);
         const real im = (real)1 / m;
-        const real ux_ = px * im, uy_ = py * im, uz_ = pz * im;
+        const real ux_ = (ct * px + st * py) * im, uy_ = (ct * py - st * px) * im, uz_ = pz * im;
         const real z2r = ux_ * ux_ - uy_ * uy_, z2i = (real)2 * ux_ * uy_;
         const real z4r = z2r * z2r - z2i * z2i, z4i = (real)2 * z2r * z2i;
         const real z5r = z4r * ux_ - z4i * uy_, z5i = z4r * uy_ + z4i * ux_;
         const real P6 = z5r * ux_ - z5i * uy_;
         as = (real)1 + eps * P6;
         const real c2 = (real)2 * eps * as * m;
-        Nx = c2 * ((real)6 * z5r - (real)6 * P6 * ux_);
-        Ny = c2 * ((real)-6 * z5i - (real)6 * P6 * uy_);
+        const real nx_ = c2 * ((real)6 * z5r - (real)6 * P6 * ux_);
+        const real ny_ = c2 * ((real)-6 * z5i - (real)6 * P6 * uy_);
+        Nx = ct * nx_ - st * ny_;
+        Ny = st * nx_ + ct * ny_;
         Nz = c2 * ((real)-6 * P6 * uz_);
     }
     const real a2 = as * as;
