@@ -67,7 +67,7 @@ def test_chmrt_growth_in_inflow_2d(lb, orc, prec):
     s.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16shift"])
 def test_chmrt_growth_in_inflow_3d_every_variant(lb, orc, prec):
     p = growth_3d()
     ref = orc.Sim(p)
