@@ -257,10 +257,10 @@ def summarize_profiles(d: str):
     traffic = {}
     lines = ["# rocprofv3 summary: fused coupled step, 3-D 192x128x128 with flow (C3)", "",
              "Commands (from the repository root, TMPDIR=/tmp):", "",
-             "    rocprofv3 --kernel-trace --stats -f csv -d gpurun_out/prof_kt -o run -- python3 bench.py --profile-run",
-             "    rocprofv3 --pmc FETCH_SIZE -f csv -d gpurun_out/prof_fetch -o run -- python3 bench.py --profile-run",
-             "    rocprofv3 --pmc WRITE_SIZE -f csv -d gpurun_out/prof_write -o run -- python3 bench.py --profile-run",
-             "    python3 bench.py --summarize-profiles gpurun_out", "",
+             f"    rocprofv3 --kernel-trace --stats -f csv -d {d}/prof_kt -o run -- python3 bench.py --profile-run",
+             f"    rocprofv3 --pmc FETCH_SIZE -f csv -d {d}/prof_fetch -o run -- python3 bench.py --profile-run",
+             f"    rocprofv3 --pmc WRITE_SIZE -f csv -d {d}/prof_write -o run -- python3 bench.py --profile-run",
+             f"    python3 bench.py --summarize-profiles {d}", "",
              f"Counter calibration on a 1 GiB device copy: FETCH_SIZE x {cal['FETCH_SIZE']:.3f}, "
              f"WRITE_SIZE x {cal['WRITE_SIZE']:.3f} (true bytes / counted bytes).", "",
              "| kernel | calls | avg us | min us | max us | read MB | write MB | algorithmic MB | measured / algorithmic | GB/s (measured bytes) |",
@@ -318,8 +318,8 @@ def summarize_sq(d: str):
     lines = ["# rocprofv3 SQ counters: fused coupled step, 3-D 192x128x128 with flow (C3)", "",
              "Commands (from the repository root, TMPDIR=/tmp):", "",
              "    rocprofv3 --pmc " + " ".join(SQ_COUNTERS) +
-             " -f csv -d gpurun_out/prof_sq -o run -- python3 bench.py --profile-run",
-             "    python3 bench.py --summarize-sq gpurun_out", "",
+             f" -f csv -d {d}/prof_sq -o run -- python3 bench.py --profile-run",
+             f"    python3 bench.py --summarize-sq {d}", "",
              "Per wavefront (one wavefront = one 64-node row segment), mean over the dispatches:", "",
              "| kernel | waves | VALU | SALU | VMEM read | VMEM write | LDS | VALU busy (4 cycles / instruction) |",
              "|---|---|---|---|---|---|---|---|"]
@@ -362,7 +362,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this solver runs on a "
-              f"single MI355X; see the sharding notes in DESIGN.md)", file=sys.stderr)
+              f"single MI355X; a multi-GPU run would shard the grid into slabs)", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

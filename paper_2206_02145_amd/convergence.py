@@ -9,7 +9,7 @@ units (the values of the other workloads: W0 = 1.5 cells <-> tau0 = 32 steps), s
 step shrinks with the square of the spacing. The profiles are compared at the physical points
 15.6, 15.8, ..., 19.4 mm, which are nodes of all four grids.
 
-    python -m paper_2206_02145_amd.convergence --levels 0.04 0.025 0.02 --out gpurun_out/conv_a.json
+    python -m paper_2206_02145_amd.convergence --levels 0.04 0.025 0.02 --out conv.json
 """
 from __future__ import annotations
 

@@ -14,7 +14,7 @@ of the reactor, which the paper shows only in figures):
 * with baffles: wall rows at y = 0 and y = ny - 1, a pressure outlet (reading R30), and plates
   across the flow upstream of the seed.
 
-    python -m paper_2206_02145_amd.habit_study --sets re tilt baffle --out gpurun_out/habit.json
+    python -m paper_2206_02145_amd.habit_study --sets re tilt baffle --out habit.json
 """
 from __future__ import annotations
 

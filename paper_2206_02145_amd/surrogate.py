@@ -1,5 +1,5 @@
 """Growth-rate surrogate: a network trained on runs of the solver itself, with the solver kept as
-the fallback and the judge of its error.
+the fallback and the reference for its error.
 
 Inputs (supersaturation U0, seed radius R, inflow velocity u_in, time t) -> 16 crystal extents
 L_k(t) along the directions 2 pi k / 16 and the 16 growth rates G_k(t) (least-squares slope of L_k
