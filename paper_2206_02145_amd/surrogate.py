@@ -251,7 +251,7 @@ def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = 
                 delivered_err_max=q(err_final.max()), solver_alone_runs_per_s=n / t_alone)
 
 
-def run_study(n_train: int = 4096, n_held: int = 256, steps: int = 4000, train_steps: int = 4000, log=None,
+def run_study(n_train: int = 4096, n_held: int = 256, steps: int = 4000, train_steps: int = 12000, log=None,
               seed_train: int = 22060, seed_held: int = 22061):
     """Generate the training and held-out runs, train both models, evaluate with fallback."""
     tr = generate(W.sweep_draws(n_train, seed=seed_train), steps=steps)
