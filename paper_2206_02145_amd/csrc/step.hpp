@@ -103,6 +103,12 @@ __host__ __device__ __forceinline__ int xmem(int x, int cx, int nx) {
     return cx == 0 ? x : (cx > 0 ? (x == 0 ? nx - 1 : x - 1) : (x == nx - 1 ? 0 : x + 1));
 }
 
+// Wall flag of node idx, the index clamped to the grid: a halo box of a grid smaller than the tile
+// reaches rows past the last one, which only nodes outside the grid read (branch-free clamp).
+__device__ __forceinline__ unsigned char wall_at(const InstDev& I, unsigned idx) {
+    return I.wall[__builtin_elementwise_min(idx, (unsigned)(I.N - 1))];
+}
+
 __device__ __forceinline__ int wrap_coord(int v, int n) {
     if (v < 0) v += n;
     if (v >= n) v -= n;
@@ -238,7 +244,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                     phi += v;
                 }
                 s_phi[b] = phi;
-                if constexpr (WALLS) s_wall[b] = I.wall[rb + (unsigned)ga];
+                if constexpr (WALLS) s_wall[b] = wall_at(I, rb + (unsigned)ga);
             }
             if (lx < 2) {
                 const int b = r * BX + 64 + lx;
@@ -250,7 +256,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                     phi += v;
                 }
                 s_phi[b] = phi;
-                if constexpr (WALLS) s_wall[b] = I.wall[rb + (unsigned)gb];
+                if constexpr (WALLS) s_wall[b] = wall_at(I, rb + (unsigned)gb);
             }
         }
     } else {
@@ -271,7 +277,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
                 phi += v;
             }
             s_phi[b] = phi;
-            if constexpr (WALLS) s_wall[b] = I.wall[rb + (unsigned)gx];
+            if constexpr (WALLS) s_wall[b] = wall_at(I, rb + (unsigned)gx);
         }
     }
     __syncthreads();
