@@ -254,7 +254,7 @@ class Solver:
         back once (lbcg_run). Returns (L_hist [samples, ndirs], mass_hist [samples] of dicts)."""
         dirs = np.zeros((0, 3)) if dirs is None else np.ascontiguousarray(dirs, dtype=np.float64)
         nd = dirs.shape[0]
-        ns = int(nsteps) // int(measure_every)
+        ns = int(nsteps) // int(measure_every) if int(measure_every) > 0 and int(nsteps) > 0 else 0
         L = np.zeros((max(ns, 1), max(nd, 1)))
         M = np.zeros((max(ns, 1), 6))
         code = lib().lbcg_run(self.handle, int(nsteps), int(measure_every), nd, _dptr(dirs) if nd else None,

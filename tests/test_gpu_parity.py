@@ -240,6 +240,29 @@ def test_run_with_diagnostics_equals_step_and_measure(lb, nsteps, every, ndirs):
     b.close()
 
 
+def test_run_edge_cases(lb):
+    """No directions (sums only), fewer steps than one interval (no sample, the steps still run),
+    and the argument errors."""
+    p = W.params(dim=2, nx=40, ny=40, U0=0.3, seed_c=(20, 20, 0), seed_R=5.0)
+    s = lb.Solver(p, "fp64")
+    L, m = s.run(30, 10)
+    assert L.shape == (3, 0) and len(m) == 3 and s.nstep == 30
+    L, m = s.run(7, 10, W.directions(4))
+    assert L.shape == (0, 4) and m == [] and s.nstep == 37
+    r = lb.Solver(p, "fp64")
+    r.step(37)
+    assert np.array_equal(r.read("raw_h"), s.read("raw_h"))
+    for bad in ((10, 0), (-1, 5)):
+        with pytest.raises(lb.LbcgError) as e:
+            s.run(*bad)
+        assert e.value.status == "EINVAL"
+    with pytest.raises(lb.LbcgError) as e:
+        s.run(10, 5, np.array([[1.0, 1.0, 0.0]]))  # not a unit vector
+    assert e.value.status == "EINVAL"
+    s.close()
+    r.close()
+
+
 def test_run_reports_nonfinite(lb):
     p = W.params(dim=2, nx=32, ny=32, seed_c=(16, 16, 0))
     s = lb.Solver(p, "fp32")
