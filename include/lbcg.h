@@ -119,8 +119,9 @@ typedef enum { LBCG_COLLISION_BGK = 0, LBCG_COLLISION_CHMRT = 1 } lbcg_collision
  * phi0 = tanh(-d / (sqrt(2) W0)) with d the signed distance to the seed: |x - c| - R for the
  * circle / sphere, and for a polygon the largest distance to its face planes, max_k n_k.(x - c) - a
  * (apothem a = R cos(pi/n)). Hexagon: face normals at tilt + 30 + 60k degrees (vertices on the axes
- * at tilt 0); rhombus (60 / 120 degrees): face normals at tilt +- 60 and tilt + 180 +- 60 degrees
- * (long diagonal, 2R, along the tilt direction). */
+ * at tilt 0); rhombus (60 / 120 degrees): face normals at tilt +- 30 and tilt + 180 +- 30 degrees,
+ * four of the hexagon's (long diagonal, 2R, across the tilt direction; the other two facets form at
+ * its acute vertices). */
 typedef enum { LBCG_SEED_CIRCLE = 0, LBCG_SEED_HEXAGON = 1, LBCG_SEED_RHOMBUS = 2 } lbcg_seed_shape;
 
 typedef struct lbcg_handle lbcg_handle;

@@ -342,10 +342,11 @@ double orc_seed_distance(const orc_params* P, double dx, double dy, double dz) {
     const double R = P->seed_R;
     if (P->seed_shape == 0) return sqrt(dx * dx + dy * dy + dz * dz) - R;
     /* hexagon: face normals at 30 + 60 k degrees (vertices on the axes); rhombus: face normals at
-     * +-60 and 180 +-60 degrees (its long diagonal along x); both turned by the tilt */
+     * +-30 and 180 +-30 degrees, four of the hexagon's (its long diagonal along y, the acute
+     * vertices where the other two facets form); both turned by the tilt (R29) */
     int nf = P->seed_shape == 1 ? 6 : 4;
     static const double hex_deg[6] = {30, 90, 150, 210, 270, 330};
-    static const double rho_deg[4] = {60, 120, 240, 300};
+    static const double rho_deg[4] = {30, 150, 210, 330};
     double apothem = R * cos(pi / (P->seed_shape == 1 ? 6.0 : 3.0));
     double d = -1e300;
     for (int k = 0; k < nf; k++) {

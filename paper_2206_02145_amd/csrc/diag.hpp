@@ -27,8 +27,8 @@ __device__ inline double seed_distance(const SeedArgs& s, double dx, double dy, 
     const double a = s.R * cos(pi / (s.shape == 1 ? 6 : 3));  // apothem
     double d = -1e300;
     for (int k = 0; k < n; k++) {
-        // hexagon: normals at 30 + 60 k degrees; rhombus: 60, 120, 240, 300 degrees
-        const double deg = s.shape == 1 ? 30.0 + 60.0 * k : (k < 2 ? 60.0 + 60.0 * k : 120.0 + 60.0 * k);
+        // hexagon: normals at 30 + 60 k degrees; rhombus: 30, 150, 210, 330 degrees (four of them)
+        const double deg = s.shape == 1 ? 30.0 + 60.0 * k : (k < 2 ? 30.0 + 120.0 * k : 210.0 + 120.0 * (k - 2));
         const double t = deg * (pi / 180.0) + s.tilt;
         d = fmax(d, cos(t) * dx + sin(t) * dy - a);
     }

@@ -876,8 +876,10 @@ def test_walls_conserve_solute_and_mass(orc):
 
 def test_faceted_seed_geometry(orc):
     """The initial hexagon lies at its apothem along its face normals and at its circumradius
-    along its vertices (Q = 1, aspect 2/sqrt3); the 60/120 rhombus has aspect sqrt3; a hexagon
-    tilted by pi/3 is the same seed; across a face the profile is the planar tanh of the model."""
+    along its vertices (Q = 1, aspect 2/sqrt3); the 60/120 rhombus lies on four of the hexagon's
+    facets (its apothem R/2 along their normals, R along the other two, where its acute vertices
+    are) and has aspect 1/sqrt3; a hexagon tilted by pi/3 is the same seed; across a face the
+    profile is the planar tanh of the model."""
     from paper_2206_02145_amd import habit as H
     R = 20.0
     base = dict(dim=2, nx=96, ny=96, seed_c=(48, 48, 0), seed_R=R)
@@ -886,7 +888,9 @@ def test_faceted_seed_geometry(orc):
     assert np.abs(h["L"] - R * math.cos(math.pi / 6)).max() < 0.01
     assert abs(h["Q"] - 1) < 1e-3 and abs(h["aspect"] - 2 / math.sqrt(3)) < 1e-3
     rh = orc.Sim(W.params(**base, seed_shape=2))
-    assert abs(H.from_extents(rh.measure(H.habit_directions())[0])["aspect"] - math.sqrt(3)) < 1e-3
+    hr = H.from_extents(rh.measure(H.habit_directions())[0])
+    assert abs(hr["aspect"] - 1 / math.sqrt(3)) < 1e-3
+    assert np.abs(hr["L"][[0, 2, 3, 5]] - R / 2).max() < 0.01 and np.abs(hr["L"][[1, 4]] - R).max() < 0.01
     turned = orc.Sim(W.params(**base, seed_shape=1, seed_tilt=math.pi / 3))
     assert np.abs(turned.phi_prev - hexa.phi_prev).max() < 1e-12
     # along +y (the normal of the face at 90 degrees) phi0 = tanh(-(k - apothem) / (sqrt2 W0))
