@@ -1,0 +1,102 @@
+"""Parity of random combinations of the solver's options against the oracle, through the C ABI:
+dimension, x faces (periodic, inflow with the zero-gradient or the pressure outlet), flow
+collision (BGK or central-Hermite MRT), storage precision, seed shape and orientation, and walls
+(random wall rows and plates, the outlet pairing rule kept). Every combination is drawn from a
+fixed seed, on small ragged grids."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2206_02145_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-4, "fp16shift": 5e-3}
+N_CASES = 16
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2206_02145_amd import lbcg
+    lbcg.lib()
+    return lbcg
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle as o
+    o.build(force=False)
+    return o
+
+
+def draw(k: int):
+    rng = np.random.default_rng(1000 + k)
+    dim = int(rng.choice([2, 3]))
+    if dim == 2:
+        nx, ny, nz = int(rng.integers(20, 70)), int(rng.integers(12, 40)), 1
+    else:
+        nx, ny, nz = int(rng.integers(12, 40)), int(rng.integers(8, 20)), int(rng.integers(6, 16))
+    flow = int(rng.integers(0, 2))
+    xbc = int(rng.choice([0, 1, 2])) if flow else int(rng.choice([0, 1]))
+    collision = int(rng.integers(0, 2)) if flow else 0
+    prec = str(rng.choice(["fp64", "fp32", "fp16shift"] if flow else ["fp64", "fp32"]))
+    shape = int(rng.integers(0, 3))
+    tilt = float(rng.uniform(0, math.pi / 3)) if shape else 0.0
+    R = float(rng.uniform(2.0, max(2.5, min(nx, ny) / 4)))
+    c = (float(rng.uniform(0.35, 0.65) * nx), float(rng.uniform(0.35, 0.65) * ny),
+         float(rng.uniform(0.35, 0.65) * nz) if dim == 3 else 0.0)
+    p = W.params(dim=dim, nx=nx, ny=ny, nz=nz, flow=flow, xbc=xbc, u_in=float(rng.uniform(0.005, 0.03)) if xbc else 0.0,
+                 U0=float(rng.uniform(0.1, 0.35)), seed_c=c, seed_R=R, seed_shape=shape, seed_tilt=tilt,
+                 collision=collision, omega_bulk=float(rng.uniform(0.8, 1.6)), nu=float(rng.uniform(0.02, 0.1)))
+    p["U_in"] = p["U0"]
+    mask = None
+    if rng.random() < 0.5:
+        mask = np.zeros((nz, ny, nx), np.uint8)
+        mask[:, 0, :] = 1                          # a wall row (plane in 3-D) at y = 0
+        if dim == 3 and rng.random() < 0.5:
+            mask[0] = 1                            # a floor
+        xb = int(rng.integers(2, max(3, int(c[0] - R - 2))))
+        y0, y1 = sorted(int(v) for v in rng.integers(1, ny, 2))
+        mask[:, y0:y1 + 1, xb] = 1                 # a plate across the flow, upstream of the seed
+        if xbc:                                    # a row's last two columns: both wall or both fluid
+            both = mask[:, :, nx - 2] | mask[:, :, nx - 1]
+            mask[:, :, nx - 2] = mask[:, :, nx - 1] = both
+    return p, prec, mask
+
+
+def relerr(a, b, floor=0.0):
+    d = max(float(np.abs(b).max()), floor)
+    return float(np.abs(a - b).max() / d) if d > 0 else float(np.abs(a).max())
+
+
+@pytest.mark.parametrize("k", range(N_CASES))
+def test_random_combination(lb, orc, k):
+    p, prec, mask = draw(k)
+    label = (f"case {k}: {p['dim']}-D {p['nx']}x{p['ny']}x{p['nz']} flow={p['flow']} xbc={p['xbc']} "
+             f"collision={p['collision']} {prec} shape={p['seed_shape']} tilt={p['seed_tilt']:.2f} "
+             f"walls={mask is not None}")
+    print(f"[combo] {label}", flush=True)
+    steps = 60
+    ref = orc.Sim(p)
+    s = lb.Solver(dict(p, walls=1 if mask is not None else 0), prec)
+    if mask is not None:
+        ref.set_walls(mask)
+        s.set_walls(mask)
+    ref.step(steps)
+    s.step(steps)
+    rf = ref.fields()
+    errs = {k2: relerr(s.read(k2), rf[k2]) for k2 in ("phi", "U", "rho")}
+    if p["flow"]:
+        # velocity scale: the flow's, the inflow's, or 1e-9 where nothing drives a flow (u* is then
+        # rounding noise on both sides: 0 on the GPU, ~1e-19 from the oracle's dense MRT solve)
+        um = max([np.abs(rf[c]).max() for c in ("ux", "uy", "uz")] + [p["u_in"], 1e-9])
+        du = max(float(np.abs(s.read(c) - rf[c]).max()) for c in ("ux", "uy", "uz"))
+        errs["u"] = du / um if um > 0 else du
+    print(f"[combo]   " + ", ".join(f"{k2}={v:.2e}" for k2, v in errs.items()), flush=True)
+    for k2, v in errs.items():
+        assert v <= TOL[prec], (label, k2, v)
+    s.close()
