@@ -255,7 +255,8 @@ lbcg_status lbcg_destroy(lbcg_handle* h);
  * inflow velocity) run many small grids; a batch steps all of them with one kernel launch per step
  * (a list of the tiles of every instance), optionally replayed from a captured HIP graph. Every
  * instance computes exactly what a single solver with the same parameters computes. All instances
- * must share dim, flow and precision; sizes and physical parameters may differ. */
+ * must share dim, flow, precision and collision; sizes, x faces and physical parameters may differ.
+ * Batches take no walls (EINVAL). */
 
 /* Device workspace bytes for n instances (0 if any parameter set is invalid). */
 size_t lbcg_batch_workspace_bytes(int n, const lbcg_params* p /* n */);
