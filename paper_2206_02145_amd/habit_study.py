@@ -45,15 +45,17 @@ def lattice(dr: float = 0.025, phys: dict = PHYS) -> dict:
 def wall_mask(nx: int, ny: int, kind: str, sx: float, sy: float, R: float) -> np.ndarray | None:
     """Synthetic geometry: 'none' (no walls, periodic in y), 'channel' (wall rows at y = 0 and
     ny - 1), 'plate' (the channel plus a plate across the flow 4 R upstream of the seed, covering
-    y within 1.5 R of the seed), 'split' (the channel plus two plates 4 R upstream that leave a gap of
-    R in front of the seed and block 3 R on either side of it)."""
+    y within 1.5 R of the seed), 'wide' (the same plate covering y within 3 R), 'split' (the channel
+    plus two plates 4 R upstream that leave a gap of R in front of the seed and block 3 R on either
+    side of it)."""
     if kind == "none":
         return None
     m = np.zeros((1, ny, nx), np.uint8)
     m[0, 0, :] = m[0, ny - 1, :] = 1
     xb = int(round(sx - 4 * R))
-    if kind == "plate":
-        m[0, int(round(sy - 1.5 * R)):int(round(sy + 1.5 * R)) + 1, xb:xb + 2] = 1
+    if kind in ("plate", "wide"):
+        half = 1.5 * R if kind == "plate" else 3.0 * R
+        m[0, int(round(sy - half)):int(round(sy + half)) + 1, xb:xb + 2] = 1
     elif kind == "split":
         m[0, int(round(sy - 3.5 * R)):int(round(sy - 0.5 * R)) + 1, xb:xb + 2] = 1
         m[0, int(round(sy + 0.5 * R)):int(round(sy + 3.5 * R)) + 1, xb:xb + 2] = 1
@@ -113,9 +115,9 @@ SETS = {
     "re": [dict(Re=0.0), dict(Re=8.6), dict(Re=17.2)],
     # seed orientation at Re 17.2
     "tilt": [dict(Re=17.2, tilt=math.radians(a)) for a in (0.0, 15.0, 30.0, 45.0)],
-    # baffles: the channel with and without plates, 2 Re x 2 tilts
+    # baffles: the channel without and with three kinds of plates, 2 Re x 2 tilts (16 cases)
     "baffle": [dict(Re=re, tilt=math.radians(t), baffle=b) for re in (8.6, 17.2) for t in (0.0, 30.0)
-               for b in ("channel", "plate", "split")],
+               for b in ("channel", "plate", "wide", "split")],
 }
 
 
