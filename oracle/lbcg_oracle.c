@@ -29,7 +29,7 @@
  *   populations copied from x = nx-2; R17 equilibrium initial populations; R23 gradient ghost at
  *   an open face = copy of the face node; R27 the h bounce-back at the inlet uses the old value of
  *   the slot it writes; R30 optional pressure outlet; R31 the central-Hermite MRT flow collision;
- *   R32 the anisotropy turns with the crystal's orientation.
+ *   R32 the anisotropy turns with the crystal's orientation; R33 optional half solute source.
  *
  * Units: lattice units, delta_t = delta_r = 1. Layout: pop[a][z][y][x], x fastest.
  */
@@ -146,6 +146,7 @@ static int check_params(const orc_params* P) {
     if (P->seed_shape < 0 || P->seed_shape > 2) return -1;
     if (P->collision < 0 || P->collision > 1) return -1;
     if (P->collision == 1 && !(P->omega_bulk > 0.0 && P->omega_bulk < 2.0)) return -1;
+    if (P->solute_source < 0 || P->solute_source > 1) return -1;
     return 0;
 }
 
@@ -577,7 +578,8 @@ static void collide_stream(const orc_params* P, const double* h, const double* g
             if (q < 0.0) q = 0.0;
             if (q > 2.0) q = 2.0;
             double tau_U = P->D * q / S.cs2 + 0.5;
-            double dphi = phi - phi_prev[i];
+            /* the source -B dphi/dt: B = 1 as Eq. (b) prints it, or 1/2 (R33) */
+            double dphi = (P->solute_source == 1 ? 0.5 : 1.0) * (phi - phi_prev[i]);
             for (int a = 0; a < S.q; a++) {
                 double cu = S.c[a][0] * us[0] + S.c[a][1] * us[1] + S.c[a][2] * us[2];
                 double geq = S.w[a] * U * (1.0 + cu / S.cs2);
@@ -773,7 +775,7 @@ int orc_measure(const orc_params* P, const double* h, const double* g, const dou
             sU += U[i];
             sP += phi_prev[i];
             Vs += 0.5 * (1.0 + phi[i]);
-            Mp += U[i] + (1.0 + phi_prev[i]);
+            Mp += U[i] + (P->solute_source == 1 ? 0.5 : 1.0) * (1.0 + phi_prev[i]);
             double um = sqrt(ux[i] * ux[i] + uy[i] * uy[i] + uz[i] * uz[i]);
             if (um > umax) umax = um;
             if (!isfinite(phi[i]) || !isfinite(U[i]) || !isfinite(rho[i])) bad += 1.0;

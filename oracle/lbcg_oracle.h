@@ -40,6 +40,8 @@ typedef struct {
     int32_t collision;                 /* flow collision: 0 BGK, 1 central-Hermite MRT (R31) */
     double omega_bulk;                 /* MRT relaxation rate of the trace of the second-order
                                         * central moment, in (0, 2) */
+    int32_t solute_source;             /* 0: the source -dphi/dt of Eq. (b) as printed; 1: half
+                                        * of it, -(1/2) dphi/dt (R33) */
 } orc_params;
 
 /* Lattice tables. kind: 0 = D2Q5, 1 = D3Q7, 2 = D2Q9, 3 = D3Q19.
@@ -74,7 +76,8 @@ int orc_fields(const orc_params* P, const double* h, const double* g, const doub
                double* U, double* rho, double* ux, double* uy, double* uz);
 
 /* Diagnostics (sums over the non-wall nodes). mass_out[6] = {sum U, sum phi_prev, V_s = sum (1+phi)/2,
- * M' = sum U + sum (1 + phi_prev), max |u*|, number of non-finite phi/U/rho values}.
+ * M' = sum U + B sum (1 + phi_prev) with B the solute source's coefficient (1, or 1/2 with
+ * solute_source = 1), max |u*|, number of non-finite phi/U/rho values}.
  * L_out[ndirs] = crystal extent along each unit direction dirs[3k..3k+2] from the seed centre.
  * Either output may be NULL. */
 int orc_measure(const orc_params* P, const double* h, const double* g, const double* f,

@@ -38,6 +38,7 @@ class OrcParams(ctypes.Structure):
         ("seed_tilt", ctypes.c_double),
         ("collision", ctypes.c_int32),
         ("omega_bulk", ctypes.c_double),
+        ("solute_source", ctypes.c_int32),
     ]
 
 
@@ -103,6 +104,7 @@ def make_params(p: dict) -> OrcParams:
     s.seed_tilt = float(p.get("seed_tilt", 0.0))
     s.collision = int(p.get("collision", 0))
     s.omega_bulk = float(p.get("omega_bulk", 1.0))
+    s.solute_source = int(p.get("solute_source", 0))
     return s
 
 

@@ -359,6 +359,35 @@ def test_solute_plus_solid_invariant(orc, dim, flow):
     assert m["Vs"] > 0 and m["nonfinite"] == 0
 
 
+@pytest.mark.parametrize("dim,flow", [(2, 0), (2, 1), (3, 0)])
+def test_half_solute_source(orc, dim, flow):
+    """R33: with the source -(1/2) dphi/dt the solute lost is exactly half the solid gained at every
+    step (d sum U = -(1/2) d sum phi_prev, from the two separate sums), so sum U + (1/2) sum
+    (1 + phi_prev) is the invariant the diagnostics report as M'; the crystal then grows faster
+    than with the printed source, whose run from the same state loses twice the solute per unit of
+    solid."""
+    n = 48 if dim == 2 else 24
+    p = W.params(dim=dim, nx=n, ny=n, nz=1 if dim == 2 else n, flow=flow, U0=0.3,
+                 seed_c=(n / 2, n / 2, n / 2 if dim == 3 else 0), seed_R=5.0)
+    out = {}
+    for src in (0, 1):
+        s = orc.Sim(dict(p, solute_source=src))
+        if flow:
+            ux = np.broadcast_to(0.02 * np.sin(2 * math.pi * np.arange(n) / n)[:, None], s.shape)
+            s.set_flow_equilibrium(1.0, 0.01 + ux, 0.005)
+        m0 = s.measure()[1]
+        s.step(200)
+        m1 = s.measure()[1]
+        dU, dP = m1["sumU"] - m0["sumU"], m1["sumPhiPrev"] - m0["sumPhiPrev"]
+        B = 0.5 if src else 1.0
+        assert dP > 0
+        assert abs(dU + B * dP) <= 1e-12 * abs(m0["sumU"])
+        assert abs(m1["Mprime"] - m0["Mprime"]) <= 1e-13 * m0["Mprime"]
+        assert abs(m0["Mprime"] - (m0["sumU"] + B * (m0["sumPhiPrev"] + s.phi_prev.size))) <= 1e-12 * m0["Mprime"]
+        out[src] = m1["Vs"]
+    assert out[1] > out[0]
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_mirror_symmetry(orc, dim):
     n = 48 if dim == 2 else 24
