@@ -104,7 +104,17 @@ typedef struct {
                           * a polygonal seed and the anisotropy, a_s = 1 + eps cos 6(theta - tilt) */
     double omega_bulk;   /* central-Hermite MRT only: relaxation rate of the trace of the second-order
                           * central moment, in (0, 2) (1: to equilibrium in one step) */
+    int32_t solute_source; /* lbcg_solute_source */
 } lbcg_params;
+
+/* Solute source (Eq. (b) and the ADE source of Section 2.2). FULL: -dphi/dt as Eq. (b) prints it,
+ * the source term of the solute populations -w_alpha (phi - phi_prev). HALF: -(1/2) dphi/dt, half
+ * the rate of change of phi, as in the thin-interface model of Karma and Rappel that the paper
+ * cites; with it the average growth rates of rhombic seeds at the paper's scale come within 8% of
+ * the ones the paper prints (Tables ljs and lax), against 0.51-0.57 of them with FULL. Either way
+ * sum U + B sum (1 + phi_prev), B = 1 or 1/2, is conserved exactly in a closed box; it is the M'
+ * of lbcg_measure. */
+typedef enum { LBCG_SOURCE_FULL = 0, LBCG_SOURCE_HALF = 1 } lbcg_solute_source;
 
 /* Flow collision (Section 2.2, flow paragraph: BGK, or the central-Hermite multiple-relaxation-time
  * operator the paper names for stability). The MRT works on central Hermite moments about u*
@@ -161,7 +171,8 @@ lbcg_status lbcg_write_field(lbcg_handle* h, int field, const void* src, size_t 
                              int src_on_device, int src_dtype);
 
 /* Diagnostics (Section 4.1.2). mass_out[6] (may be NULL) receives, accumulated in binary64:
- * {sum U, sum phi_prev, V_s = sum (1+phi)/2, M' = sum U + sum (1 + phi_prev), max |u*|,
+ * {sum U, sum phi_prev, V_s = sum (1+phi)/2, M' = sum U + B sum (1 + phi_prev) (B of
+ *  lbcg_solute_source), max |u*|,
  *  number of nodes with non-finite phi, U or rho}.
  * L_out[ndirs] (may be NULL when ndirs = 0) receives the crystal extent along each unit
  * direction dirs[3k..3k+2] from the seed centre: the first phi = 0 crossing of a ray sampled

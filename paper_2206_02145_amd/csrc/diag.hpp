@@ -190,7 +190,7 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_kernel(InstDev I, int par,
         acc[0] += U;
         acc[1] += psi_prev - 1.0;
         acc[2] += 0.5 * (double)psi;      // (1 + phi) / 2
-        acc[3] += U + psi_prev;           // U + (1 + phi_prev)
+        acc[3] += U + I.kd[K_SRC] * psi_prev;  // U + B (1 + phi_prev)
         const double um = sqrt((double)ux * ux + (double)uy * uy + (double)uz * uz);
         acc[4] = fmax(acc[4], um);
         if (!isfinite((double)psi) || !isfinite((double)Ut) || !isfinite((double)rho)) acc[5] += 1.0;

@@ -101,6 +101,8 @@ void validate(const lbcg_params* p) {
     if (!(p->grad_eps2 >= 0)) throw Error(LBCG_EINVAL, "grad_eps2 must be >= 0");
     if (p->collision == LBCG_COLLISION_CHMRT && !(p->omega_bulk > 0 && p->omega_bulk < 2))
         throw Error(LBCG_EUNSTABLE, "omega_bulk must lie in (0, 2)");
+    if (p->solute_source != LBCG_SOURCE_FULL && p->solute_source != LBCG_SOURCE_HALF)
+        throw Error(LBCG_EINVAL, "solute_source must be 0 (full) or 1 (half)");
 }
 
 struct Layout {
@@ -191,6 +193,7 @@ InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling&
     I.kd[K_OMB] = p->collision == LBCG_COLLISION_CHMRT ? p->omega_bulk : 1.0;
     I.kd[K_CT] = p->seed_tilt == 0.0 ? 1.0 : std::cos(p->seed_tilt);
     I.kd[K_ST] = p->seed_tilt == 0.0 ? 0.0 : std::sin(p->seed_tilt);
+    I.kd[K_SRC] = p->solute_source == LBCG_SOURCE_HALF ? 0.5 : 1.0;
     for (int k = 0; k < 16; k++) I.kf[k] = (float)I.kd[k];
     return I;
 }

@@ -309,7 +309,7 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
                 real q = two_m_psi;
                 q = q < (real)0 ? (real)0 : (q > (real)2 ? (real)2 : q);
                 const real inv_tau_U = (real)1 / (DU * q + (real)0.5);
-                const real dphi = psi - pp;
+                const real dphi = kconst<real>(I, K_SRC) * (psi - pp);
                 real gk[S::Q];
                 real gsum = 0;
 #pragma unroll

@@ -88,6 +88,7 @@ enum : int {
     K_OMB,        // trace relaxation rate of the central-Hermite MRT flow collision
     K_CT,         // cos and sin of the crystal's orientation (the anisotropy's frame)
     K_ST,
+    K_SRC,        // B of the solute source -B dphi/dt: 1, or 1/2 (both exact scalings)
 };
 template <typename real> __device__ __forceinline__ real kconst(const InstDev& I, int k) {
     if constexpr (sizeof(real) == 4) return I.kf[k];
@@ -516,12 +517,12 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         }
     }
 
-    // ---- solute: advection-diffusion LB with source -w dphi/dt ----
+    // ---- solute: advection-diffusion LB with source -w B dphi/dt ----
     {
         real q = two_m_psi;  // 1 - phi, clamped to [0, 2]
         q = q < (real)0 ? (real)0 : (q > (real)2 ? (real)2 : q);
         const real inv_tau_U = (real)1 / (kconst<real>(I, K_DQ) * q + (real)0.5);
-        const real dphi = psi - pp;
+        const real dphi = kconst<real>(I, K_SRC) * (psi - pp);
         const real Uin2 = kconst<real>(I, K_UIN2);
         real gk[S::Q];
         real gsum = 0;
@@ -534,7 +535,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             gk[a] = gv[a] - (gv[a] - geq) * inv_tau_U - wa * dphi;
             if (a) gsum += gk[a];
         }
-        gk[0] = (Ut - dphi) - gsum;  // solute balance of the node: sum_a g*_a - U0 = U - U0 - dphi
+        gk[0] = (Ut - dphi) - gsum;  // solute balance of the node: sum_a g*_a - U0 = U - U0 - B dphi
 #pragma unroll
         for (int a = 0; a < S::Q; a++)
             if (push_ok(S::c(a, 0)) && !to_wall(swall, a)) ST(gout, a, row(S::c(a, 1), S::c(a, 2)), x, gk[a]);

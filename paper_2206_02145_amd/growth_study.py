@@ -10,7 +10,7 @@ L_avg is the mean of the six normal lengths measured every hour and G_th the slo
 fit (lbcg_growth_rates); the per-normal slopes are reported too (the rhombus's four sides and the
 two facets forming at its acute vertices).
 
-    python -m paper_2206_02145_amd.growth_study --out growth.json
+    python -m paper_2206_02145_amd.growth_study --source 1 --out growth.json
 """
 from __future__ import annotations
 
@@ -31,8 +31,10 @@ PAPER_G_VS_U = {0.06: 0.057, 0.085: 0.0871, 0.11: 0.1136, 0.15: 0.1553, 0.2: 0.2
 PAPER_G_VS_P = {6.9: 0.0567, 6.96: 0.0575, 8.4: 0.0592, 8.8: 0.0598}                    # Table lax, U = 0.06
 
 
-def case(U: float, P: float, dr: float = 0.025, hours: float | None = None, phys: dict = PHYS) -> dict:
-    """Parameters and step counts of one case: supersaturation U, rhombus perimeter P (mm)."""
+def case(U: float, P: float, dr: float = 0.025, hours: float | None = None, phys: dict = PHYS,
+         source: int = 0) -> dict:
+    """Parameters and step counts of one case: supersaturation U, rhombus perimeter P (mm), solute
+    source (0: -dphi/dt as Eq. (b) prints it, 1: -(1/2) dphi/dt, reading R33)."""
     k = W.BASE["W0"] ** 2 / W.BASE["tau0"]
     W0c = phys["W0"] / dr
     tau0 = W0c ** 2 / k
@@ -40,10 +42,10 @@ def case(U: float, P: float, dr: float = 0.025, hours: float | None = None, phys
     nx, ny = round(phys["Lx"] / dr), round(phys["Ly"] / dr)
     R = (P / 4) * math.cos(math.pi / 6) / dr  # circumradius (half the long diagonal) in cells
     p = W.params(dim=2, nx=nx, ny=ny, U0=U, U_in=U, seed_c=(nx / 2, ny / 2, 0.0), seed_R=R, seed_shape=2)
-    p.update(W0=W0c, tau0=tau0, D=phys["D"] * dt / dr ** 2)
+    p.update(W0=W0c, tau0=tau0, D=phys["D"] * dt / dr ** 2, solute_source=int(source))
     per_hour = round(3600 / dt)
     h = phys["hours"] if hours is None else hours
-    return dict(params=p, steps=round(h * per_hour), per_hour=per_hour, dt=dt, dr=dr, U=U, P=P)
+    return dict(params=p, steps=round(h * per_hour), per_hour=per_hour, dt=dt, dr=dr, U=U, P=P, source=int(source))
 
 
 def run(c: dict, precision: str = "fp64", log=None) -> dict:
@@ -59,11 +61,11 @@ def run(c: dict, precision: str = "fp64", log=None) -> dict:
     secs = time.perf_counter() - t0
     s.close()
     to_mm_h = c["dr"] / c["dt"] * 3600.0  # cells per step -> mm per hour
-    out = dict(U=c["U"], P=c["P"], steps=c["steps"], seconds=secs, G_th=float(G_avg) * to_mm_h,
+    out = dict(U=c["U"], P=c["P"], source=c["source"], steps=c["steps"], seconds=secs, G_th=float(G_avg) * to_mm_h,
                G_normals=(np.asarray(G) * to_mm_h).tolist(), R2=np.asarray(R2).tolist(),
                L_mm=(np.vstack([L0[None], L]) * c["dr"]).tolist())
     if log:
-        log(f"U {c['U']:.3f} P {c['P']:.2f} mm: G_th {out['G_th']:.4f} mm/h, normals "
+        log(f"source {c['source']} U {c['U']:.3f} P {c['P']:.2f} mm: G_th {out['G_th']:.4f} mm/h, normals "
             + " ".join(f"{g:.4f}" for g in out["G_normals"]) + f" ({secs:.1f} s)")
     return out
 
@@ -73,16 +75,17 @@ def main(argv=None):
     ap.add_argument("--dr", type=float, default=0.025)
     ap.add_argument("--hours", type=float, default=None)
     ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--source", type=int, default=0, help="0: full solute source (Eq. (b)), 1: half (R33)")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
-    res = dict(vs_U=[], vs_P=[])
+    res = dict(source=args.source, vs_U=[], vs_P=[])
     for U, g in PAPER_G_VS_U.items():
-        r = run(case(U, 6.9, args.dr, args.hours), args.precision, log)
+        r = run(case(U, 6.9, args.dr, args.hours, source=args.source), args.precision, log)
         r["paper_G_th"] = g
         res["vs_U"].append(r)
     for P, g in PAPER_G_VS_P.items():
-        r = run(case(0.06, P, args.dr, args.hours), args.precision, log)
+        r = run(case(0.06, P, args.dr, args.hours, source=args.source), args.precision, log)
         r["paper_G_th"] = g
         res["vs_P"].append(r)
     Us = np.array([r["U"] for r in res["vs_U"]])

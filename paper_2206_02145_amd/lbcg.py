@@ -34,7 +34,7 @@ class lbcg_params(ctypes.Structure):
         ("U_inlet", ctypes.c_double), ("seed_center", ctypes.c_double * 3),
         ("seed_radius", ctypes.c_double), ("grad_eps2", ctypes.c_double),
         ("seed_shape", ctypes.c_int32), ("collision", ctypes.c_int32), ("seed_tilt", ctypes.c_double),
-        ("omega_bulk", ctypes.c_double),
+        ("omega_bulk", ctypes.c_double), ("solute_source", ctypes.c_int32),
     ]
 
 
@@ -136,6 +136,7 @@ def make_params(p: dict, precision: str = "fp32") -> lbcg_params:
     s.seed_radius, s.grad_eps2 = p["seed_R"], p["grad_eps2"]
     s.seed_shape, s.seed_tilt = int(p.get("seed_shape", 0)), float(p.get("seed_tilt", 0.0))
     s.collision, s.omega_bulk = int(p.get("collision", 0)), float(p.get("omega_bulk", 1.0))
+    s.solute_source = int(p.get("solute_source", 0))
     return s
 
 

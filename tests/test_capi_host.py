@@ -67,6 +67,8 @@ def create_status(p, prec="fp32", nbytes=None):
     (dict(flow=0, collision=1), "EINVAL"),        # the MRT collision is a flow option
     (dict(flow=1, collision=1, omega_bulk=2.0), "EUNSTABLE"),
     (dict(flow=1, collision=1, omega_bulk=float("nan")), "EINVAL"),
+    (dict(solute_source=2), "EINVAL"),
+    (dict(solute_source=-1), "EINVAL"),
 ])
 def test_create_rejects_bad_parameters(change, expect):
     p = W.params(**change)

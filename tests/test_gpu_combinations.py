@@ -1,7 +1,7 @@
 """Parity of random combinations of the solver's options against the oracle, through the C ABI:
 dimension, x faces (periodic, inflow with the zero-gradient or the pressure outlet), flow
-collision (BGK or central-Hermite MRT), storage precision, seed shape and orientation, and walls
-(random wall rows and plates, the outlet pairing rule kept). Every combination is drawn from a
+collision (BGK or central-Hermite MRT), storage precision, seed shape and orientation, walls
+(random wall rows and plates, the outlet pairing rule kept) and the solute source (full or half). Every combination is drawn from a
 fixed seed, on small ragged grids."""
 import math
 
@@ -65,6 +65,7 @@ def draw(k: int):
         if xbc:                                    # a row's last two columns: both wall or both fluid
             both = mask[:, :, nx - 2] | mask[:, :, nx - 1]
             mask[:, :, nx - 2] = mask[:, :, nx - 1] = both
+    p["solute_source"] = int(rng.integers(0, 2))   # drawn last: the earlier draws keep their values
     return p, prec, mask
 
 
@@ -78,7 +79,7 @@ def test_random_combination(lb, orc, k):
     p, prec, mask = draw(k)
     label = (f"case {k}: {p['dim']}-D {p['nx']}x{p['ny']}x{p['nz']} flow={p['flow']} xbc={p['xbc']} "
              f"collision={p['collision']} {prec} shape={p['seed_shape']} tilt={p['seed_tilt']:.2f} "
-             f"walls={mask is not None}")
+             f"walls={mask is not None} source={p['solute_source']}")
     print(f"[combo] {label}", flush=True)
     steps = 60
     ref = orc.Sim(p)

@@ -1,7 +1,8 @@
-"""The no-flow growth-rate study (paper_2206_02145_amd.growth_study) at a reduced scale: 0.04 mm
-spacing, 6 simulated hours, binary64 on the GPU. As in the paper's Tables `ss`, `lax` and `ljs`:
+"""The no-flow growth-rate study (paper_2206_02145_amd.growth_study) on the GPU in binary64. At a
+reduced scale (0.04 mm spacing, 6 simulated hours), as in the paper's Tables `ss`, `lax` and `ljs`:
 at low supersaturation the rhombus's four sides grow well ahead of the two facets forming at its
-acute vertices, and the average growth rate rises linearly with the supersaturation."""
+acute vertices, and the average growth rate rises linearly with the supersaturation. At the paper's
+scale: the average growth rates with either solute source against Table `ljs`."""
 import numpy as np
 import pytest
 
@@ -36,3 +37,26 @@ def test_growth_rate_is_linear_in_supersaturation(runs):
     fit = np.polyfit(U, G, 1)
     resid = G - np.polyval(fit, U)
     assert np.abs(resid).max() < 0.05 * G.max(), (G, fit)
+
+
+
+@pytest.fixture(scope="module")
+def paper_scale():
+    """U = 0.06 and 0.2 at the paper's scale (0.025 mm, 12 h; ~8 s a case), both solute sources."""
+    from paper_2206_02145_amd import growth_study as G
+    return {(src, U): G.run(G.case(U, 6.9, source=src), "fp64", log=lambda m: print(f"[growth] {m}", flush=True))
+            for src in (0, 1) for U in (0.06, 0.2)}
+
+
+def test_half_source_reaches_the_papers_growth_rates(paper_scale):
+    """Reading R33. With the source of Eq. (b) as printed the average growth rates come out at about
+    half of the ones the paper prints (Table ljs); with half the source the crystal consumes half
+    the solute per unit of solid, grows about twice as fast, and lands within 12% of the table."""
+    from paper_2206_02145_amd import growth_study as G
+    for U in (0.06, 0.2):
+        full, half, paper = paper_scale[(0, U)]["G_th"], paper_scale[(1, U)]["G_th"], G.PAPER_G_VS_U[U]
+        print(f"[growth] U {U}: G_th {full:.4f} (full source), {half:.4f} (half source), paper {paper:.4f} mm/h",
+              flush=True)
+        assert 0.4 < full / paper < 0.7, (U, full)
+        assert 1.5 < half / full < 2.5, (U, half / full)
+        assert abs(half / paper - 1) < 0.12, (U, half)
