@@ -65,8 +65,9 @@ def wall_mask(nx: int, ny: int, kind: str, sx: float, sy: float, R: float) -> np
 
 
 def case(Re: float, tilt: float = 0.0, baffle: str = "none", dr: float = 0.025, hours: float | None = None,
-         phys: dict = PHYS) -> dict:
-    """Parameters, wall mask and step count of one study case."""
+         phys: dict = PHYS, source: int = 0) -> dict:
+    """Parameters, wall mask and step count of one study case; source selects the solute source
+    (0: -dphi/dt as Eq. (b) prints it, 1: -(1/2) dphi/dt, reading R33)."""
     lt = lattice(dr, phys)
     nx, ny = round(phys["Lx"] / dr), round(phys["Ly"] / dr)
     P = phys["perimeter"] / dr             # seed perimeter in cells
@@ -76,12 +77,12 @@ def case(Re: float, tilt: float = 0.0, baffle: str = "none", dr: float = 0.025, 
     m = wall_mask(nx, ny, baffle, sx, sy, R)
     p = W.params(dim=2, nx=nx, ny=ny, flow=1, xbc=2 if m is not None else 1, u_in=u_in, U0=phys["U"],
                  U_in=phys["U"], seed_c=(sx, sy, 0.0), seed_R=R, seed_shape=1, seed_tilt=tilt,
-                 walls=1 if m is not None else 0)
+                 walls=1 if m is not None else 0, solute_source=int(source))
     p.update(W0=lt["W0"], tau0=lt["tau0"], D=lt["D"])
     h = phys["hours"] if hours is None else hours
     per_hour = round(3600 / lt["dt"])
     return dict(params=p, mask=m, steps=round(h * per_hour), per_hour=per_hour,
-                dt=lt["dt"], dr=dr, Re=Re, tilt=tilt, baffle=baffle, u_in=u_in, R=R)
+                dt=lt["dt"], dr=dr, Re=Re, tilt=tilt, baffle=baffle, u_in=u_in, R=R, source=int(source))
 
 
 def run(c: dict, precision: str = "fp64", log=None) -> dict:
@@ -96,17 +97,17 @@ def run(c: dict, precision: str = "fp64", log=None) -> dict:
     secs = time.perf_counter() - t0
     s.close()
     rows = [habit.from_extents(l) for l in L]
-    out = dict(Re=c["Re"], tilt=c["tilt"], baffle=c["baffle"], u_in=c["u_in"], steps=c["steps"], seconds=secs,
+    out = dict(Re=c["Re"], tilt=c["tilt"], baffle=c["baffle"], source=c["source"], u_in=c["u_in"], steps=c["steps"], seconds=secs,
                hours=[(k + 1) * c["per_hour"] * c["dt"] / 3600 for k in range(len(rows))],
                Q=[r["Q"] for r in rows], aspect=[r["aspect"] for r in rows],
                upstream=[r["upstream"] for r in rows],
                L_mm=[(np.asarray(r["L"]) * c["dr"]).tolist() for r in rows],
                L_axes_mm=[(np.asarray(l[6:10]) * c["dr"]).tolist() for l in L],
-               Vs=[m["Vs"] for m in mass])
+               Vs=[m["Vs"] for m in mass], L_avg_mm=[r["L_avg"] * c["dr"] for r in rows])
     if log:
-        log(f"Re {c['Re']:5.1f} tilt {math.degrees(c['tilt']):4.1f} {c['baffle']:8s}: Q {out['Q'][-1]:.3f}, "
+        log(f"source {c['source']} Re {c['Re']:5.1f} tilt {math.degrees(c['tilt']):4.1f} {c['baffle']:8s}: Q {out['Q'][-1]:.3f}, "
             f"aspect {out['aspect'][-1]:.3f}, upstream/downstream {out['upstream'][-1]:.3f} after "
-            f"{out['hours'][-1]:.1f} h ({secs:.1f} s)")
+            f"{out['hours'][-1]:.1f} h, L_avg {out['L_avg_mm'][-1]:.3f} mm ({secs:.1f} s)")
     return out
 
 
@@ -127,12 +128,14 @@ def main(argv=None):
     ap.add_argument("--dr", type=float, default=0.025)
     ap.add_argument("--hours", type=float, default=None)
     ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--source", type=int, default=0, help="0: full solute source (Eq. (b)), 1: half (R33)")
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     res = {}
     for name in args.sets:
-        res[name] = [run(case(dr=args.dr, hours=args.hours, **kw), args.precision, log) for kw in SETS[name]]
+        res[name] = [run(case(dr=args.dr, hours=args.hours, source=args.source, **kw), args.precision, log)
+                     for kw in SETS[name]]
         with open(args.out, "w") as fh:
             json.dump(res, fh)
     return 0
