@@ -2,6 +2,7 @@
 // forward / backward / Adam sequencing of the kernels in mlp.hpp on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
@@ -42,6 +43,8 @@ template <typename F> lbcg_status mguard(F&& fn) {
 }
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+constexpr int SPLIT_MAX = 8;  // most K splits of a weight-gradient GEMM
 
 struct Layer {
     int in, out;
@@ -90,6 +93,7 @@ struct lbcg_mlp {
     float* t;                // gathered targets [maxB x w[nl]/2]
     bf16* dz[2];             // back-propagated gradients (bf16) [maxB x max width]
     float* partial;          // loss partial sums
+    float* split;            // split-K partial sums of a weight gradient [SPLIT_MAX x max in*out]
     int64_t step;
 };
 
@@ -117,13 +121,18 @@ Plan plan_of(int nl, const int* w, int maxB) {
     P.take((size_t)maxB * mw * 2);
     P.take((size_t)maxB * mw * 2);
     P.take((size_t)((maxB * (w[nl] / 2) + 255) / 256 + 1) * 4);  // partials
+    size_t nwmax = 0;
+    for (int l = 0; l < nl; l++) nwmax = std::max(nwmax, (size_t)w[l] * w[l + 1]);
+    P.take((size_t)SPLIT_MAX * nwmax * 4);  // split-K partial sums
     return P;
 }
 
 int blocks(long long n) { return (int)((n + 255) / 256); }
 
-void gemm(int epi, const GemmArgs& g, hipStream_t s) {
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+void gemm(int epi, GemmArgs g, hipStream_t s) {
+    constexpr int TK = 32;
+    if (g.kchunk <= 0) g.kchunk = (g.K + TK - 1) / TK * TK;  // one split
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, (g.K + g.kchunk - 1) / g.kchunk);
     switch (epi) {
         case EPI_FWD_HIDDEN: hipLaunchKernelGGL(gemm_bf16<EPI_FWD_HIDDEN>, grid, dim3(256), 0, s, g); break;
         case EPI_FWD_OUT: hipLaunchKernelGGL(gemm_bf16<EPI_FWD_OUT>, grid, dim3(256), 0, s, g); break;
@@ -177,9 +186,23 @@ float backward(lbcg_mlp* m, int B) {
         gw.B = m->a[l];  // B(k = b, j) = a[b, j]
         gw.ldb_k = L.in;
         gw.ldb_n = 1;
-        gw.out_f32 = L.gW;
-        gemm(EPI_DW, gw, m->stream);
-        hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks(L.out)), dim3(256), 0, m->stream, B, L.out, m->dz[cur], L.gb);
+        // split K = B over up to SPLIT_MAX workgroup layers (B = 1024: 8 x 128): a weight
+        // gradient has only (out/64) x (in/64) output tiles
+        const int S = std::max(1, std::min(SPLIT_MAX, B / 128));
+        gw.kchunk = ((B + S - 1) / S + 31) / 32 * 32;
+        const int nsplit = (B + gw.kchunk - 1) / gw.kchunk;
+        const long long nw = (long long)L.out * L.in;
+        if (nsplit > 1) {
+            gw.out_f32 = m->split;
+            gw.split_stride = nw;
+            gemm(EPI_DW, gw, m->stream);
+            hipLaunchKernelGGL(split_sum_kernel, dim3(blocks(nw)), dim3(256), 0, m->stream, nw, nsplit, m->split, L.gW);
+        } else {
+            gw.out_f32 = L.gW;
+            gemm(EPI_DW, gw, m->stream);
+        }
+        hipLaunchKernelGGL(bias_grad_kernel, dim3((L.out + 63) / 64), dim3(64 * BG_WAVES), 0, m->stream, B, L.out,
+                           m->dz[cur], L.gb);
         if (l > 0) {
             // dz_{l-1} = (dz W) * silu'(z_{l-1})
             GemmArgs gx{};
@@ -269,6 +292,7 @@ lbcg_status lbcg_mlp_create(int nlayers, const int* widths, int max_batch, void*
         m->dz[0] = (bf16*)nxt();
         m->dz[1] = (bf16*)nxt();
         m->partial = (float*)nxt();
+        m->split = (float*)nxt();
         MCHK(hipMemsetAsync(m->ws, 0, P.total, m->stream));
         MCHK(hipStreamSynchronize(m->stream));
     });

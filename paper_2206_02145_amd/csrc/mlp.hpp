@@ -36,14 +36,58 @@ struct GemmArgs {
     float* z;           // pre-activation (forward: written; backward: read, previous layer)
     bf16* out_bf16;     // activation / back-propagated gradient
     float* out_f32;     // output layer / weight gradient
+    int kchunk;          // K range of one split (blockIdx.z), a multiple of the K tile; >= K: no split
+    long long split_stride;  // weight gradient: elements between the partial sums of two splits
 };
+
+constexpr int GEMM_TK = 32;
+
+// Stage a 64 x 32 operand tile X(r, k) = X[r * ld_r + k * ld_k], rows r0 .. r0 + 63 (< R) and
+// k0 .. k0 + 31 (< kend), into sX[r][k], zero outside. The 256 threads take 8 consecutive elements
+// each along the operand's unit-stride index (one 16-byte load when vec: that stride is 1, the
+// other a multiple of 8 and the base 16-byte aligned); neither stride 1: one element at a time.
+__device__ inline void stage_tile(bf16 (*sX)[GEMM_TK + 8], const bf16* X, long long ld_r, long long ld_k, int r0,
+                                  int R, int k0, int kend, bool kfast, bool rfast, bool vec, int tid) {
+    if (kfast) {  // 8 consecutive k of one row
+        const int r = tid >> 2, k = (tid & 3) * 8;
+        const int gr = r0 + r, gk = k0 + k;
+        bf16x8 v;
+        if (vec && gr < R && gk + 8 <= kend) {
+            v = *reinterpret_cast<const bf16x8*>(X + gr * ld_r + gk);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; j++) v[j] = (gr < R && gk + j < kend) ? X[gr * ld_r + gk + j] : (bf16)0.0f;
+        }
+        *reinterpret_cast<bf16x8*>(&sX[r][k]) = v;
+    } else if (rfast) {  // 8 consecutive rows of one k
+        const int r = (tid & 7) * 8, k = tid >> 3;
+        const int gr = r0 + r, gk = k0 + k;
+        bf16x8 v;
+        if (vec && gk < kend && gr + 8 <= R) {
+            v = *reinterpret_cast<const bf16x8*>(X + gk * ld_k + gr);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; j++) v[j] = (gk < kend && gr + j < R) ? X[gk * ld_k + gr + j] : (bf16)0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) sX[r + j][k] = v[j];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int idx = tid + 256 * e;
+            const int r = idx / GEMM_TK, k = idx % GEMM_TK;
+            const int gr = r0 + r, gk = k0 + k;
+            sX[r][k] = (gr < R && gk < kend) ? X[gr * ld_r + gk * ld_k] : (bf16)0.0f;
+        }
+    }
+}
 
 // C = A B for a 64 x 64 tile per workgroup (4 wavefronts x 16 rows, 4 MFMA blocks of 16 columns).
 template <int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
-    constexpr int TM = 64, TN = 64, TK = 32;
-    __shared__ bf16 sA[TM][TK + 8];  // A tile, k contiguous
-    __shared__ bf16 sB[TN][TK + 8];  // B tile transposed (n, k), k contiguous
+    constexpr int TM = 64, TN = 64, TK = GEMM_TK;
+    __shared__ __align__(16) bf16 sA[TM][TK + 8];  // A tile, k contiguous
+    __shared__ __align__(16) bf16 sB[TN][TK + 8];  // B tile transposed (n, k), k contiguous
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
@@ -51,18 +95,18 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
 #pragma unroll
     for (int b = 0; b < 4; b++) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    const int kbeg = blockIdx.z * g.kchunk;
+    const int kend = min(g.K, kbeg + g.kchunk);
+    // consecutive threads walk each operand's unit-stride index (coalesced, 16-byte loads)
+    const bool a_kf = g.lda_k == 1, a_rf = !a_kf && g.lda_i == 1;
+    const bool b_kf = g.ldb_k == 1, b_rf = !b_kf && g.ldb_n == 1;
+    const auto aligned = [](const bf16* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    const bool a_vec = aligned(g.A) && (a_kf ? g.lda_i % 8 == 0 : g.lda_k % 8 == 0);
+    const bool b_vec = aligned(g.B) && (b_kf ? g.ldb_n % 8 == 0 : g.ldb_k % 8 == 0);
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
         // stage: 64x32 of A and 32x64 of B (8 elements each per thread), zero outside the matrix
-#pragma unroll
-        for (int e = 0; e < 8; e++) {
-            const int idx = tid + 256 * e;  // 0 .. 2047
-            const int i = idx / TK, k = idx % TK;
-            const int gi = m0 + i, gk = k0 + k;
-            sA[i][k] = (gi < g.M && gk < g.K) ? g.A[gi * g.lda_i + gk * g.lda_k] : (bf16)0.0f;
-            const int n = idx / TK;  // 0 .. 63
-            const int gn = n0 + n;
-            sB[n][k] = (gn < g.N && gk < g.K) ? g.B[gk * g.ldb_k + gn * g.ldb_n] : (bf16)0.0f;
-        }
+        stage_tile(sA, g.A, g.lda_i, g.lda_k, m0, g.M, k0, kend, a_kf, a_rf, a_vec, tid);
+        stage_tile(sB, g.B, g.ldb_n, g.ldb_k, n0, g.N, k0, kend, b_kf, b_rf, b_vec, tid);
         __syncthreads();
         // fragments: lane holds A(i = lane%16, k = 8*(lane/16) + j), B(k = 8*(lane/16) + j, n = lane%16)
         const int r = lane & 15, kq = 8 * (lane >> 4);
@@ -98,7 +142,7 @@ __global__ __launch_bounds__(256) void gemm_bf16(GemmArgs g) {
                 // dA of the previous layer times the derivative of its activation
                 g.out_bf16[o] = to_bf16(c * dsilu(g.z[o]));
             } else {
-                g.out_f32[o] = c;
+                g.out_f32[blockIdx.z * g.split_stride + o] = c;
             }
         }
     }
@@ -134,13 +178,35 @@ __global__ __launch_bounds__(256) void nll_kernel(int B, int D, const float* y, 
     if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
-// Bias gradient: db[n] = sum_b dz[b, n] (fixed order), one thread per column.
-__global__ __launch_bounds__(256) void bias_grad_kernel(int B, int N, const bf16* dz, float* db) {
-    const int n = blockIdx.x * 256 + threadIdx.x;
-    if (n >= N) return;
-    float s = 0.f;
-    for (int b = 0; b < B; b++) s += (float)dz[(long long)b * N + n];
-    db[n] = s;
+// Sum of the split-K partial products of the weight gradient, in split order.
+__global__ __launch_bounds__(256) void split_sum_kernel(long long n, int S, const float* part, float* out) {
+    const long long i = blockIdx.x * 256LL + threadIdx.x;
+    if (i >= n) return;
+    float s = part[i];
+    for (int k = 1; k < S; k++) s += part[k * n + i];
+    out[i] = s;
+}
+
+// Bias gradient db[n] = sum_b dz[b, n]: a workgroup of 16 wavefronts takes 64 columns (lane =
+// column, coalesced rows); wavefront w sums rows w, w + 16, ..., then the 16 partial sums are added
+// in wavefront order (a fixed order for a given B).
+constexpr int BG_WAVES = 16;
+__global__ __launch_bounds__(64 * BG_WAVES) void bias_grad_kernel(int B, int N, const bf16* dz, float* db) {
+    __shared__ float s[BG_WAVES][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + lane;
+    float acc = 0.f;
+    if (n < N) {
+#pragma unroll 8
+        for (int b = wv; b < B; b += BG_WAVES) acc += (float)dz[(long long)b * N + n];
+    }
+    s[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && n < N) {
+        float t = 0.f;
+        for (int w = 0; w < BG_WAVES; w++) t += s[w][lane];
+        db[n] = t;
+    }
 }
 
 // Gather rows idx[b] of the dataset X (rows of width W) into out (fp32 -> bf16 for the input layer).
