@@ -268,7 +268,7 @@ PROFILE_GROUPS = [
 ]
 
 
-def summarize_profiles(d: str):
+def summarize_profiles(d: str, out_dir: str = os.path.join(ROOT, "profiles")):
     """Turn the csv of three rocprofv3 runs of `bench.py --profile-run` (kernel trace + stats,
     --pmc FETCH_SIZE, --pmc WRITE_SIZE) into the summaries of PROFILE_GROUPS under profiles/ and
     profiles/traffic.json. Counter values are KiB per dispatch; each is scaled by what the same
@@ -335,13 +335,13 @@ def summarize_profiles(d: str):
         gbs = (rd_mb + wr_mb) * 1e6 / (st.mean(ts) * 1e-6) / 1e9 if fe and wr else float("nan")
         table[tag] = (f"| {tag} | {len(ts)} | {st.mean(ts):.1f} | {min(ts):.1f} | {max(ts):.1f} | "
                       f"{rd_mb:.1f} | {wr_mb:.1f} | {alg} | {ratio} | {gbs:.0f} | {alg_gbs} |")
-    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    os.makedirs(out_dir, exist_ok=True)
     for fname, title, keep in PROFILE_GROUPS:
         lines = [f"# rocprofv3 summary: {title}", ""] + head + [table[t] for t in sorted(table) if keep(t)]
-        with open(os.path.join(ROOT, "profiles", fname), "w") as fh:
+        with open(os.path.join(out_dir, fname), "w") as fh:
             fh.write("\n".join(lines) + "\n")
         print("\n".join(lines) + "\n")
-    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+    with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
         json.dump(traffic, fh, indent=1)
 
 
