@@ -126,3 +126,15 @@ def test_params_struct_layout_matches_the_header(tmp_path):
     assert vals[0] == ctypes.sizeof(lbcg.lbcg_params)
     for n, off in zip(names, vals[1:]):
         assert getattr(lbcg.lbcg_params, n).offset == off, n
+
+
+def test_largest_grid_is_accepted_and_one_node_more_is_not():
+    """2^29 - 1 nodes (2089 x 1103 x 233) is the largest grid: a population plane of binary64 then
+    spans 2^32 - 8 bytes, the reach of the kernels' 32-bit byte offsets."""
+    assert 2089 * 1103 * 233 == 2 ** 29 - 1
+    for prec, flow in (("fp64", 0), ("fp32", 1), ("fp16shift", 1)):
+        big = W.params(dim=3, nx=2089, ny=1103, nz=233, flow=flow)
+        nb = lbcg.lbcg_workspace_bytes(lbcg.make_params(big, prec))
+        planes = 2 * (2 * 7) + 1
+        assert nb >= planes * (2 ** 29 - 1) * (8 if prec == "fp64" else 4), (prec, nb)
+        assert lbcg.lbcg_workspace_bytes(lbcg.make_params(dict(big, nx=2090), prec)) == 0, prec
