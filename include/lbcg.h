@@ -320,7 +320,9 @@ lbcg_status lbcg_mlp_forward(lbcg_mlp* m, int B, const float* x, float* y);
 lbcg_status lbcg_mlp_grads(lbcg_mlp* m, int B, const float* X, const float* T, const int* idx, int rows,
                            float* host_grads, float* loss_out);
 /* One training step: gather, forward, loss, backward, Adam (bias-corrected; the step count is
- * kept by the handle). *loss_out (may be NULL) gets the batch loss before the update. Synchronises. */
+ * kept by the handle). *loss_out gets the batch loss before the update and the call synchronises;
+ * with loss_out NULL the step is only enqueued on the handle's stream (X, T and idx must then stay
+ * valid until the stream reaches it). */
 lbcg_status lbcg_mlp_train_step(lbcg_mlp* m, int B, const float* X, const float* T, const int* idx, int rows,
                                 float lr, float beta1, float beta2, float eps, float* loss_out);
 lbcg_status lbcg_mlp_destroy(lbcg_mlp* m);

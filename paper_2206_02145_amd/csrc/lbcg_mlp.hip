@@ -167,8 +167,9 @@ void forward(lbcg_mlp* m, int B) {
     }
 }
 
-// loss + backward for the batch in m->a[0] / m->t (forward already run); returns the loss
-float backward(lbcg_mlp* m, int B) {
+// loss + backward for the batch in m->a[0] / m->t (forward already run); the loss stays on the
+// device as per-block partial sums (loss_of reads it back)
+void backward(lbcg_mlp* m, int B) {
     const int D = m->w[m->nl] / 2;
     const int nb = blocks((long long)B * D);
     hipLaunchKernelGGL(nll_kernel, dim3(nb), dim3(256), 0, m->stream, B, D, m->y, m->t, m->dz[0], m->partial);
@@ -221,6 +222,11 @@ float backward(lbcg_mlp* m, int B) {
             cur ^= 1;
         }
     }
+}
+
+// the last batch's loss: sum of the partials in block order (synchronises)
+float loss_of(lbcg_mlp* m, int B) {
+    const int nb = blocks((long long)B * (m->w[m->nl] / 2));
     std::vector<float> part(nb);
     MCHK(hipMemcpyAsync(part.data(), m->partial, sizeof(float) * nb, hipMemcpyDeviceToHost, m->stream));
     MCHK(hipStreamSynchronize(m->stream));
@@ -369,8 +375,8 @@ lbcg_status lbcg_mlp_grads(lbcg_mlp* m, int B, const float* X, const float* T, c
         if (B < 1 || B > m->maxB || rows < 1) throw MErr(LBCG_EINVAL, "batch size out of range");
         gather(m, B, X, T, idx, rows);
         forward(m, B);
-        const float loss = backward(m, B);
-        if (loss_out) *loss_out = loss;
+        backward(m, B);
+        if (loss_out) *loss_out = loss_of(m, B);
         if (host_grads) {
             float* p = host_grads;
             for (Layer& L : m->layers) {
@@ -394,7 +400,7 @@ lbcg_status lbcg_mlp_train_step(lbcg_mlp* m, int B, const float* X, const float*
             throw MErr(LBCG_EINVAL, "bad Adam hyper-parameters");
         gather(m, B, X, T, idx, rows);
         forward(m, B);
-        const float loss = backward(m, B);
+        backward(m, B);
         m->step++;
         const float c1 = 1.f - std::pow(beta1, (float)m->step), c2 = 1.f - std::pow(beta2, (float)m->step);
         for (Layer& L : m->layers) {
@@ -405,7 +411,7 @@ lbcg_status lbcg_mlp_train_step(lbcg_mlp* m, int B, const float* X, const float*
                                (bf16*)nullptr, L.gb, L.mb, L.vb, lr, beta1, beta2, eps, c1, c2);
         }
         MCHK(hipGetLastError());
-        if (loss_out) *loss_out = loss;
+        if (loss_out) *loss_out = loss_of(m, B);  // the partials are not touched by the update
     });
 }
 

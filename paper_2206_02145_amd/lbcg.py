@@ -436,13 +436,16 @@ class MLP:
                                    int(X_dev.shape[0]), _fptr(g), ctypes.byref(loss)), "lbcg_mlp_grads")
         return g, loss.value
 
-    def train_step(self, X_dev, T_dev, idx_dev, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> float:
+    def train_step(self, X_dev, T_dev, idx_dev, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, want_loss=True):
+        """One Adam step on the rows idx_dev of (X_dev, T_dev); returns the batch loss, or None
+        without synchronising when want_loss is False."""
         loss = ctypes.c_float()
         check(lib().lbcg_mlp_train_step(self.handle, int(idx_dev.shape[0]), ctypes.c_void_p(X_dev.data_ptr()),
                                         ctypes.c_void_p(T_dev.data_ptr()), ctypes.c_void_p(idx_dev.data_ptr()),
-                                        int(X_dev.shape[0]), lr, beta1, beta2, eps, ctypes.byref(loss)),
+                                        int(X_dev.shape[0]), lr, beta1, beta2, eps,
+                                        ctypes.byref(loss) if want_loss else None),
               "lbcg_mlp_train_step")
-        return loss.value
+        return loss.value if want_loss else None
 
     def close(self):
         if getattr(self, "handle", None):

@@ -126,18 +126,26 @@ class Surrogate:
         Td = torch.tensor((Y - self.mean) / self.std, dtype=torch.float32, device="cuda")
         rng = np.random.default_rng(seed)
         nrow = X.shape[0]
+        # every step's rows (a fresh permutation per epoch, the tail that does not fill a batch
+        # skipped), uploaded once so that the steps queue up without host round trips
+        batches = np.empty((steps, min(batch, nrow)), dtype=np.int32)
         perm = rng.permutation(nrow)
         pos = 0
-        losses = []
-        t0 = time.perf_counter()
         for k in range(steps):
             if pos + batch > nrow:
                 perm = rng.permutation(nrow)
                 pos = 0
-            idx = torch.tensor(perm[pos:pos + batch].astype(np.int32), device="cuda")
+            batches[k] = perm[pos:pos + batch]
             pos += batch
+        idx_all = torch.tensor(batches, device="cuda")
+        losses = []
+        t0 = time.perf_counter()
+        for k in range(steps):
             lr_k = lr * (0.1 if k >= 0.75 * steps else 1.0)
-            losses.append(self.net.train_step(Xd, Td, idx, lr=lr_k))
+            want = k >= steps - 50 or (log is not None and k % 500 == 0)  # the loss costs a synchronisation
+            loss = self.net.train_step(Xd, Td, idx_all[k], lr=lr_k, want_loss=want)
+            if want:
+                losses.append(loss)
             if log and (k % 500 == 0 or k == steps - 1):
                 log(f"surrogate step {k}: loss {losses[-1]:.4f}")
         torch.cuda.synchronize()
