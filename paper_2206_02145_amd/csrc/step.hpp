@@ -235,30 +235,37 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             const int gy = wrap_coord(y0 + by - 1, ny);
             const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
             const unsigned rb = (unsigned)((gz * ny + gy) * nx);
-            {
-                const int b = r * BX + lx;
-                real phi = 0;
+            const int b = r * BX + lx;
+            real phi = 0;
 #pragma unroll
-                for (int a = 0; a < S::Q; a++) {
-                    const real v = LD(hin, a, rb, csel(ca, S::c(a, 0)));
-                    s_h[a][b] = v;
-                    phi += v;
-                }
-                s_phi[b] = phi;
-                if constexpr (WALLS) s_wall[b] = wall_at(I, rb + (unsigned)ga);
+            for (int a = 0; a < S::Q; a++) {
+                const real v = LD(hin, a, rb, csel(ca, S::c(a, 0)));
+                s_h[a][b] = v;
+                phi += v;
             }
-            if (lx < 2) {
-                const int b = r * BX + 64 + lx;
-                real phi = 0;
+            s_phi[b] = phi;
+            if constexpr (WALLS) s_wall[b] = wall_at(I, rb + (unsigned)ga);
+        }
+        // box columns 64 and 65 of the wavefront's rows in one load per plane: lanes 2j and 2j + 1
+        // take its j-th row (the row base is then per lane: a vector offset, not the scalar one)
+        constexpr int RW = (BY * BZ + NW - 1) / NW;  // box rows per wavefront
+        static_assert(2 * RW <= 64, "x-halo lanes");
+        const int rj = lyz + (lx >> 1) * NW;
+        if (lx < 2 * RW && rj < BY * BZ) {
+            const int by = rj % BY, bz = rj / BY;
+            const int gy = wrap_coord(y0 + by - 1, ny);
+            const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
+            const unsigned rb = (unsigned)((gz * ny + gy) * nx);
+            const int b = rj * BX + 64 + (lx & 1);
+            real phi = 0;
 #pragma unroll
-                for (int a = 0; a < S::Q; a++) {
-                    const real v = LD(hin, a, rb, csel(cb, S::c(a, 0)));
-                    s_h[a][b] = v;
-                    phi += v;
-                }
-                s_phi[b] = phi;
-                if constexpr (WALLS) s_wall[b] = wall_at(I, rb + (unsigned)gb);
+            for (int a = 0; a < S::Q; a++) {
+                const real v = hin.template ld<real>(a, rb + (unsigned)csel(cb, S::c(a, 0)));
+                s_h[a][b] = v;
+                phi += v;
             }
+            s_phi[b] = phi;
+            if constexpr (WALLS) s_wall[b] = wall_at(I, rb + (unsigned)gb);
         }
     } else {
         for (int b = tid; b < NB; b += NT) {
