@@ -266,7 +266,8 @@ lbcg_status lbcg_destroy(lbcg_handle* h);
  * inflow velocity) run many small grids; a batch steps all of them with one kernel launch per step
  * (a list of the tiles of every instance), optionally replayed from a captured HIP graph. Every
  * instance computes exactly what a single solver with the same parameters computes. All instances
- * must share dim, flow, precision and collision; sizes, x faces and physical parameters may differ.
+ * must share dim, flow, precision and collision; sizes, x faces, the solute source and physical
+ * parameters may differ.
  * Batches take no walls (EINVAL). */
 
 /* Device workspace bytes for n instances (0 if any parameter set is invalid). */

@@ -65,3 +65,13 @@ def test_baffle_geometry(kind):
         assert m[0, int(round(sy)), cols].all()                     # a plate in front of the seed
         half = (rows.max() - rows.min()) / 2
         assert abs(half - (1.5 if kind == "plate" else 3.0) * R) <= 1.0
+
+
+def test_studies_pass_the_solute_source():
+    """Both studies default to the source of Eq. (b) as printed and take the half source (R33)."""
+    assert growth_study.case(0.06, 6.9)["params"].get("solute_source", 0) == 0
+    assert growth_study.case(0.06, 6.9, source=1)["params"]["solute_source"] == 1
+    assert habit_study.case(17.2)["params"].get("solute_source", 0) == 0
+    assert habit_study.case(17.2, source=1)["params"]["solute_source"] == 1
+    from paper_2206_02145_amd import lbcg
+    assert lbcg.make_params(growth_study.case(0.06, 6.9, source=1)["params"], "fp64").solute_source == 1
