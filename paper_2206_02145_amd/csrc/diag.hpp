@@ -44,8 +44,8 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev I, int par, SeedArgs 
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
     const long long N = I.N;
-    const Planes<real> h(pick(I.h, par), N), g(pick(I.g, par), N), pp(I.phi_prev, N);
-    const Planes<fst> f(pick(I.f, par), N);
+    const Planes<real> h(pick(I.h, par), I.Np), g(pick(I.g, par), I.Np), pp(I.phi_prev, N);
+    const Planes<fst> f(pick(I.f, par), I.Np);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % I.nx);
@@ -80,8 +80,7 @@ __device__ inline void node_moments(const InstDev& I, int par, long long i, real
                                     real& rho, real& usx, real& usy, real& usz) {
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
-    const long long N = I.N;
-    const Planes<real> h(pick(I.h, par), N), g(pick(I.g, par), N);
+    const Planes<real> h(pick(I.h, par), I.Np), g(pick(I.g, par), I.Np);
     const int x = (int)(i % I.nx);
     const unsigned row = (unsigned)(i - x);
     psi = 0;
@@ -95,7 +94,7 @@ __device__ inline void node_moments(const InstDev& I, int par, long long i, real
     rho = 1;
     usx = usy = usz = 0;
     if constexpr (FLOW) {
-        const Planes<fst> f(pick(I.f, par), N);
+        const Planes<fst> f(pick(I.f, par), I.Np);
         real drho = 0, mx = 0, my = 0, mz = 0;
 #pragma unroll
         for (int a = 0; a < V::Q; a++) {
@@ -245,7 +244,7 @@ __device__ inline double phi_node(const InstDev& I, const real* h, int x, int y,
     const long long row = ((long long)z * I.ny + y) * I.nx;
     double psi = 0;
 #pragma unroll
-    for (int a = 0; a < S::Q; a++) psi += (double)h[a * I.N + row + xmem(x, S::c(a, 0), I.nx)];
+    for (int a = 0; a < S::Q; a++) psi += (double)h[a * I.Np + row + xmem(x, S::c(a, 0), I.nx)];
     return psi - 1.0;
 }
 

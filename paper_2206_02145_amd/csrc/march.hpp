@@ -51,9 +51,9 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
     const bool active = xin && y < ny;
     const bool xopen = I.xopen != 0;
 
-    const Planes<real> hin(pick(I.h, par), N), hout(pick(I.h, par ^ 1), N);
-    const Planes<real> gin(pick(I.g, par), N), gout(pick(I.g, par ^ 1), N);
-    const Planes<fst> fin(pick(I.f, par), N), fout(pick(I.f, par ^ 1), N);
+    const Planes<real> hin(pick(I.h, par), I.Np), hout(pick(I.h, par ^ 1), I.Np);
+    const Planes<real> gin(pick(I.g, par), I.Np), gout(pick(I.g, par ^ 1), I.Np);
+    const Planes<fst> fin(pick(I.f, par), I.Np), fout(pick(I.f, par ^ 1), I.Np);
     const Planes<real> pprev(I.phi_prev, N);
 
     auto wrapz = [&](int v) { return wrap_coord(v, nz); };

@@ -57,6 +57,7 @@ struct InstDev {
     int zc;                       // planes per workgroup of the z-marching kernel
     int zband;                    // block tiles: z tile-layers per band of the tile order (<= 1: none)
     long long N;                  // nodes
+    long long Np;                 // plane stride of the population arrays (nodes; >= N)
     void* h[2];                   // ping-pong population arrays, planes [a][z][y][x]
     void* g[2];
     void* f[2];
@@ -176,10 +177,10 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     }
     const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
 
-    const Planes<real, AUX> hin(pick(I.h, par), N), hout(pick(I.h, par ^ 1), N);
-    const Planes<real, AUX, LAUX> gin(pick(I.g, par), N), gout(pick(I.g, par ^ 1), N);
+    const Planes<real, AUX> hin(pick(I.h, par), I.Np), hout(pick(I.h, par ^ 1), I.Np);
+    const Planes<real, AUX, LAUX> gin(pick(I.g, par), I.Np), gout(pick(I.g, par ^ 1), I.Np);
     const Planes<real, 0, LAUX> pprev(I.phi_prev, N);
-    const Planes<fst, AUX, LAUX> fin(pick(I.f, par), N), fout(pick(I.f, par ^ 1), N);
+    const Planes<fst, AUX, LAUX> fin(pick(I.f, par), I.Np), fout(pick(I.f, par ^ 1), I.Np);
     // node (row + col) of plane a; with ROW the row is wave-uniform
     auto LD = [&](const auto& P, int a, unsigned row, int col) -> real {
         if constexpr (ROW) return P.template ldr<real>(a, row, (unsigned)col);
