@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev I, int par, SeedArgs 
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
     const long long N = I.N;
-    const Planes<real> h(pick(I.h, par), I.Np), g(pick(I.g, par), I.Np), pp(I.phi_prev, N);
+    const Planes<real> h(pick(I.h, par), I.Np), g(pick(I.g, par), I.Np), pp(I.phi_prev, I.Nm);
     const Planes<fst> f(pick(I.f, par), I.Np);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
          i += (long long)gridDim.x * blockDim.x) {
@@ -52,10 +52,10 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev I, int par, SeedArgs 
         const long long r = i / I.nx;
         const int y = (int)(r % I.ny);
         const int z = (int)(r / I.ny);
-        const unsigned row = (unsigned)(i - x);
+        const unsigned row = (unsigned)(r * I.pitch);
         const double dx = x - s.cx, dy = y - s.cy, dz = (DIM == 3) ? z - s.cz : 0.0;
         const double phi0 = tanh(-seed_distance<DIM>(s, dx, dy, dz) / (sqrt(2.0) * s.W0));
-        pp.st(0, (unsigned)i, (real)(phi0 + 1.0));
+        pp.st(0, row + (unsigned)x, (real)(phi0 + 1.0));
 #pragma unroll
         for (int a = 0; a < S::Q; a++) {
             const unsigned m = row + xmem(x, S::c(a, 0), I.nx);
@@ -74,6 +74,11 @@ __global__ __launch_bounds__(256) void init_kernel(InstDev I, int par, SeedArgs 
     }
 }
 
+// Stored index of the node with dense index i = (z ny + y) nx + x.
+__device__ __forceinline__ long long stored_node(const InstDev& I, long long i) {
+    return (i / I.nx) * I.pitch + i % I.nx;
+}
+
 // Moments of one node in the compute precision: psi = phi + 1, Ut = U - U0, rho and u*.
 template <int DIM, bool FLOW, typename real, typename fst>
 __device__ inline void node_moments(const InstDev& I, int par, long long i, real& psi, real& Ut,
@@ -82,7 +87,7 @@ __device__ inline void node_moments(const InstDev& I, int par, long long i, real
     using V = typename Lattices<DIM>::V;
     const Planes<real> h(pick(I.h, par), I.Np), g(pick(I.g, par), I.Np);
     const int x = (int)(i % I.nx);
-    const unsigned row = (unsigned)(i - x);
+    const unsigned row = (unsigned)((i / I.nx) * I.pitch);
     psi = 0;
     Ut = 0;
 #pragma unroll
@@ -123,7 +128,7 @@ __global__ __launch_bounds__(256) void field_kernel(InstDev I, int par, int fiel
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
          i += (long long)gridDim.x * blockDim.x) {
         if (field == 6) {
-            out[i] = (out_t)((double)pp[i] - 1.0);  // psi_prev = phi_prev + 1 (no column shift)
+            out[i] = (out_t)((double)pp[stored_node(I, i)] - 1.0);  // psi_prev = phi_prev + 1 (no column shift)
             continue;
         }
         real psi, Ut, rho, ux, uy, uz;
@@ -137,25 +142,27 @@ __global__ __launch_bounds__(256) void field_kernel(InstDev I, int par, int fiel
 // One stored plane to out, decoded to the plain layout: value(x) = stored(column xmem(x, cx)) + shift
 // (h: -w, g: w U0, f: w).
 template <typename real, typename st, typename out_t>
-__global__ __launch_bounds__(256) void raw_read_kernel(const st* src, long long n, int nx, int cx, double shift,
-                                                       out_t* out) {
-    const Planes<st> P(src, n);
+__global__ __launch_bounds__(256) void raw_read_kernel(const st* src, long long n, int nx, int pitch, long long nm,
+                                                       int cx, double shift, out_t* out) {
+    const Planes<st> P(src, nm);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx);
-        out[i] = (out_t)((double)P.template ld<real>(0, (unsigned)(i - x) + xmem(x, cx, nx)) + shift);
+        const unsigned row = (unsigned)((i / nx) * pitch);
+        out[i] = (out_t)((double)P.template ld<real>(0, row + xmem(x, cx, nx)) + shift);
     }
 }
 
 // One plane from the plain layout, encoded: stored(column xmem(x, cx)) = value(x) - shift, rounded once.
 template <typename real, typename st, typename in_t>
-__global__ __launch_bounds__(256) void raw_write_kernel(st* dst, long long n, int nx, int cx, double shift,
-                                                        const in_t* in) {
-    const Planes<st> P(dst, n);
+__global__ __launch_bounds__(256) void raw_write_kernel(st* dst, long long n, int nx, int pitch, long long nm, int cx,
+                                                        double shift, const in_t* in) {
+    const Planes<st> P(dst, nm);
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx);
-        P.st(0, (unsigned)(i - x) + xmem(x, cx, nx), (real)((double)in[i] - shift));
+        const unsigned row = (unsigned)((i / nx) * pitch);
+        P.st(0, row + xmem(x, cx, nx), (real)((double)in[i] - shift));
     }
 }
 
@@ -181,11 +188,12 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_kernel(InstDev I, int par,
     double acc[RED_VALUES] = {0, 0, 0, 0, 0, 0};
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
          i += (long long)gridDim.x * blockDim.x) {
-        if (I.wall && I.wall[i]) continue;  // the sums cover the fluid and the crystal
+        const long long m = stored_node(I, i);
+        if (I.wall && I.wall[m]) continue;  // the sums cover the fluid and the crystal
         real psi, Ut, rho, ux, uy, uz;
         node_moments<DIM, FLOW, real, fst>(I, par, i, psi, Ut, rho, ux, uy, uz);
         const double U = (double)Ut + I.U0;
-        const double psi_prev = (double)pp[i];  // phi_prev + 1
+        const double psi_prev = (double)pp[m];  // phi_prev + 1
         acc[0] += U;
         acc[1] += psi_prev - 1.0;
         acc[2] += 0.5 * (double)psi;      // (1 + phi) / 2
@@ -241,7 +249,7 @@ __global__ __launch_bounds__(64) void reduce_final(const double* partials, int n
 template <int DIM, typename real>
 __device__ inline double phi_node(const InstDev& I, const real* h, int x, int y, int z) {
     using S = typename Lattices<DIM>::S;
-    const long long row = ((long long)z * I.ny + y) * I.nx;
+    const long long row = ((long long)z * I.ny + y) * I.pitch;
     double psi = 0;
 #pragma unroll
     for (int a = 0; a < S::Q; a++) psi += (double)h[a * I.Np + row + xmem(x, S::c(a, 0), I.nx)];

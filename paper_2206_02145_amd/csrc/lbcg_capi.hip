@@ -119,8 +119,18 @@ size_t plane_stride(size_t N) {
     return s * 8 < (size_t(1) << 32) ? s : N;
 }
 
+// Stored row length: nx rounded up to 64 nodes, so that every row starts on a 256-byte boundary in
+// binary32 (128 bytes for binary16 flow storage) and a wavefront's 64-node segment covers whole
+// cache lines (rows of other lengths cost up to 1.5x per node on MI355X). nx itself where the
+// padded binary64 plane would reach 2^32 bytes.
+int row_pitch(const lbcg_params* p) {
+    const size_t r = ((size_t)p->nx + 63) / 64 * 64;
+    return (size_t)p->nz * p->ny * r * 8 < (size_t(1) << 32) ? (int)r : p->nx;
+}
+size_t stored_nodes(const lbcg_params* p) { return (size_t)p->nz * p->ny * row_pitch(p); }
+
 Layout layout_of(const lbcg_params* p) {
-    const size_t N0 = (size_t)p->nx * p->ny * p->nz, N = plane_stride(N0);
+    const size_t N0 = (size_t)p->nx * p->ny * p->nz, Nm = stored_nodes(p), N = plane_stride(Nm);
     const size_t rs = real_size(p->precision), fs = fstore_size(p->precision);
     Layout L{};
     size_t off = 0;
@@ -132,13 +142,13 @@ Layout layout_of(const lbcg_params* p) {
     for (int k = 0; k < 2; k++) L.h[k] = take(qs_of(p->dim) * N * rs);
     for (int k = 0; k < 2; k++) L.g[k] = take(qs_of(p->dim) * N * rs);
     for (int k = 0; k < 2; k++) L.f[k] = p->flow ? take(qf_of(p->dim) * N * fs) : 0;
-    L.phi_prev = take(N0 * rs);
+    L.phi_prev = take(Nm * rs);
     L.staging = take(N0 * 8);
     L.partials = take((RED_BLOCKS + 1) * RED_VALUES * 8);  // block partials, then the final values
     L.dirs = take(MAX_DIRS * 3 * 8);
     L.out = take((RED_VALUES + MAX_DIRS) * 8);
     L.hist = take(HIST_DOUBLES * 8);
-    L.wall = p->walls ? take(N0) : 0;
+    L.wall = p->walls ? take(Nm) : 0;
     L.total = off;
     return L;
 }
@@ -169,7 +179,9 @@ InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling&
     I.zc = T.TZ;
     I.zband = T.march ? 0 : T.zband;
     I.N = (long long)p->nx * p->ny * p->nz;
-    I.Np = (long long)plane_stride((size_t)I.N);
+    I.pitch = row_pitch(p);
+    I.Nm = (long long)stored_nodes(p);
+    I.Np = (long long)plane_stride((size_t)I.Nm);
     for (int k = 0; k < 2; k++) {
         I.h[k] = ws + L.h[k];
         I.g[k] = ws + L.g[k];
@@ -500,30 +512,34 @@ std::string variant_name(const Variant& v) {
 template <typename real, typename st>
 void raw_read_t(const lbcg_params& p, const void* base, int field, int a, long long N, void* out, int dtype,
                 hipStream_t s) {
-    const st* src = (const st*)base + (size_t)a * plane_stride((size_t)N);
+    const int pitch = row_pitch(&p);
+    const long long nm = (long long)stored_nodes(&p);
+    const st* src = (const st*)base + (size_t)a * plane_stride((size_t)nm);
     const int nb = grid_for(N, 256, 65536);
     const int cx = plane_cx(p, field, a);
     const double sh = plane_shift(p, field, a);
     if (dtype == LBCG_DTYPE_F64)
-        hipLaunchKernelGGL((raw_read_kernel<real, st, double>), dim3(nb), dim3(256), 0, s, src, N, p.nx, cx, sh,
+        hipLaunchKernelGGL((raw_read_kernel<real, st, double>), dim3(nb), dim3(256), 0, s, src, N, p.nx, pitch, nm, cx, sh,
                            (double*)out);
     else
-        hipLaunchKernelGGL((raw_read_kernel<real, st, float>), dim3(nb), dim3(256), 0, s, src, N, p.nx, cx, sh,
+        hipLaunchKernelGGL((raw_read_kernel<real, st, float>), dim3(nb), dim3(256), 0, s, src, N, p.nx, pitch, nm, cx, sh,
                            (float*)out);
 }
 
 template <typename real, typename st>
 void raw_write_t(const lbcg_params& p, void* base, int field, int a, long long N, const void* in, int dtype,
                  hipStream_t s) {
-    st* dst = (st*)base + (size_t)a * plane_stride((size_t)N);
+    const int pitch = row_pitch(&p);
+    const long long nm = (long long)stored_nodes(&p);
+    st* dst = (st*)base + (size_t)a * plane_stride((size_t)nm);
     const int nb = grid_for(N, 256, 65536);
     const int cx = plane_cx(p, field, a);
     const double sh = plane_shift(p, field, a);
     if (dtype == LBCG_DTYPE_F64)
-        hipLaunchKernelGGL((raw_write_kernel<real, st, double>), dim3(nb), dim3(256), 0, s, dst, N, p.nx, cx, sh,
+        hipLaunchKernelGGL((raw_write_kernel<real, st, double>), dim3(nb), dim3(256), 0, s, dst, N, p.nx, pitch, nm, cx, sh,
                            (const double*)in);
     else
-        hipLaunchKernelGGL((raw_write_kernel<real, st, float>), dim3(nb), dim3(256), 0, s, dst, N, p.nx, cx, sh,
+        hipLaunchKernelGGL((raw_write_kernel<real, st, float>), dim3(nb), dim3(256), 0, s, dst, N, p.nx, pitch, nm, cx, sh,
                            (const float*)in);
 }
 
@@ -583,7 +599,7 @@ const BatchKit& batch_kit_for(int dim, int kind, int prec) {
 // Per-instance population buffers inside a batch workspace (the single-grid layout without its
 // staging and diagnostics areas).
 Layout instance_layout(const lbcg_params* p, size_t& off) {
-    const size_t N0 = (size_t)p->nx * p->ny * p->nz, N = plane_stride(N0);
+    const size_t Nm = stored_nodes(p), N = plane_stride(Nm);
     const size_t rs = real_size(p->precision), fs = fstore_size(p->precision);
     Layout L{};
     auto take = [&](size_t bytes) {
@@ -594,7 +610,7 @@ Layout instance_layout(const lbcg_params* p, size_t& off) {
     for (int k = 0; k < 2; k++) L.h[k] = take(qs_of(p->dim) * N * rs);
     for (int k = 0; k < 2; k++) L.g[k] = take(qs_of(p->dim) * N * rs);
     for (int k = 0; k < 2; k++) L.f[k] = p->flow ? take(qf_of(p->dim) * N * fs) : 0;
-    L.phi_prev = take(N0 * rs);
+    L.phi_prev = take(Nm * rs);
     return L;
 }
 
@@ -1119,13 +1135,15 @@ lbcg_status lbcg_set_walls(lbcg_handle* h, const uint8_t* mask, size_t bytes, in
             for (size_t r = 0; r < N / nx; r++)
                 if ((hm[r * nx + nx - 2] != 0) != (hm[r * nx + nx - 1] != 0))
                     throw Error(LBCG_EINVAL, "a row's last two columns must be both wall or both fluid");
-        HIPCHK(hipMemcpyAsync(h->ws + h->L.wall, hm, N, hipMemcpyHostToDevice, h->stream));  // hm is host memory
+        // hm is host memory, dense rows of nx; the device mask has rows of the stored pitch
+        HIPCHK(hipMemcpy2DAsync(h->ws + h->L.wall, (size_t)h->inst.pitch, hm, nx, nx, N / nx, hipMemcpyHostToDevice,
+                                h->stream));
         // Wall nodes are never written: give both ping-pong copies the current state so that they
         // stay frozen whichever copy is current.
         const lbcg_params& p = h->p;
         const size_t rs = real_size(p.precision), fs = fstore_size(p.precision);
         const int cur = h->par, oth = h->par ^ 1;
-        const size_t Np = plane_stride(N);
+        const size_t Np = plane_stride(stored_nodes(&p));
         HIPCHK(hipMemcpyAsync(h->ws + h->L.h[oth], h->ws + h->L.h[cur], qs_of(p.dim) * Np * rs,
                               hipMemcpyDeviceToDevice, h->stream));
         HIPCHK(hipMemcpyAsync(h->ws + h->L.g[oth], h->ws + h->L.g[cur], qs_of(p.dim) * Np * rs,
@@ -1154,13 +1172,13 @@ constexpr char STATE_MAGIC[8] = {'L', 'B', 'C', 'G', 'S', 'T', 'A', 'T'};
 // (offset in the workspace, bytes) of each stored array of the current copy, in blob order
 std::vector<std::pair<size_t, size_t>> state_parts(const lbcg_handle* h) {
     const lbcg_params& p = h->p;
-    const size_t N = (size_t)h->inst.N, Np = plane_stride(N);
+    const size_t Nm = stored_nodes(&p), Np = plane_stride(Nm);
     const size_t rs = real_size(p.precision), fs = fstore_size(p.precision);
     std::vector<std::pair<size_t, size_t>> v;
     v.push_back({h->L.h[h->par], qs_of(p.dim) * Np * rs});
     v.push_back({h->L.g[h->par], qs_of(p.dim) * Np * rs});
     if (p.flow) v.push_back({h->L.f[h->par], qf_of(p.dim) * Np * fs});
-    v.push_back({h->L.phi_prev, N * rs});
+    v.push_back({h->L.phi_prev, Nm * rs});
     return v;
 }
 
@@ -1181,7 +1199,7 @@ lbcg_status lbcg_state_save(lbcg_handle* h, void* dst, size_t dst_bytes, int dst
         if (dst_bytes < state_bytes_of(h)) throw Error(LBCG_ENOMEM, "destination smaller than lbcg_state_bytes");
         StateHeader H{};
         std::memcpy(H.magic, STATE_MAGIC, 8);
-        H.version = 2;
+        H.version = 3;
         H.dim = h->p.dim;
         H.nx = h->p.nx;
         H.ny = h->p.ny;
@@ -1215,7 +1233,7 @@ lbcg_status lbcg_state_load(lbcg_handle* h, const void* src, size_t src_bytes, i
         } else {
             std::memcpy(&H, in, sizeof H);
         }
-        if (std::memcmp(H.magic, STATE_MAGIC, 8) != 0 || H.version != 2)
+        if (std::memcmp(H.magic, STATE_MAGIC, 8) != 0 || H.version != 3)
             throw Error(LBCG_EINVAL, "not a checkpoint of this library (magic or version)");
         if (H.dim != h->p.dim || H.nx != h->p.nx || H.ny != h->p.ny || H.nz != h->p.nz || H.flow != h->p.flow ||
             H.precision != h->p.precision || H.xbc != h->p.xbc)

@@ -40,7 +40,6 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
     const int x = tid % NXP;
     const int ly = tid / NXP;
     const int nx = I.nx, ny = I.ny, nz = I.nz;
-    const long long N = I.N;
     const int tiy = tile % I.tiles_y;
     const int tiz = tile / I.tiles_y;
     const int y0 = tiy * TY;
@@ -54,11 +53,11 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
     const Planes<real> hin(pick(I.h, par), I.Np), hout(pick(I.h, par ^ 1), I.Np);
     const Planes<real> gin(pick(I.g, par), I.Np), gout(pick(I.g, par ^ 1), I.Np);
     const Planes<fst> fin(pick(I.f, par), I.Np), fout(pick(I.f, par ^ 1), I.Np);
-    const Planes<real> pprev(I.phi_prev, N);
+    const Planes<real> pprev(I.phi_prev, I.Nm);
 
     auto wrapz = [&](int v) { return wrap_coord(v, nz); };
     auto wrapy = [&](int v) { return wrap_coord(v, ny); };
-    auto node = [&](int xx, int yy, int zz) { return (unsigned)((zz * ny + yy) * nx + xx); };
+    auto node = [&](int xx, int yy, int zz) { return (unsigned)((zz * ny + yy) * I.pitch + xx); };
     // x neighbour inside the row for phi and the old-value term: wrap, or the face copy at an open face
     const int xm = x > 0 ? x - 1 : (xopen ? 0 : nx - 1);
     const int xp = x < nx - 1 ? x + 1 : (xopen ? nx - 1 : 0);

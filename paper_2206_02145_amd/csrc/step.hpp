@@ -57,7 +57,9 @@ struct InstDev {
     int zc;                       // planes per workgroup of the z-marching kernel
     int zband;                    // block tiles: z tile-layers per band of the tile order (<= 1: none)
     long long N;                  // nodes
-    long long Np;                 // plane stride of the population arrays (nodes; >= N)
+    int pitch;                    // stored row length (nodes; >= nx): node (x, y, z) at (z ny + y) pitch + x
+    long long Nm;                 // stored nodes of a plane, nz ny pitch
+    long long Np;                 // plane stride of the population arrays (>= Nm)
     void* h[2];                   // ping-pong population arrays, planes [a][z][y][x]
     void* g[2];
     void* f[2];
@@ -108,7 +110,7 @@ __host__ __device__ __forceinline__ int xmem(int x, int cx, int nx) {
 // Wall flag of node idx, the index clamped to the grid: a halo box of a grid smaller than the tile
 // reaches rows past the last one, which only nodes outside the grid read (branch-free clamp).
 __device__ __forceinline__ unsigned char wall_at(const InstDev& I, unsigned idx) {
-    return I.wall[__builtin_elementwise_min(idx, (unsigned)(I.N - 1))];
+    return I.wall[__builtin_elementwise_min(idx, (unsigned)(I.Nm - 1))];
 }
 
 __device__ __forceinline__ int wrap_coord(int v, int n) {
@@ -158,8 +160,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     __shared__ unsigned char s_wall[WALLS ? NB : 1];
 
     const int tid = threadIdx.x;
-    const int nx = I.nx, ny = I.ny, nz = I.nz;
-    const long long N = I.N;
+    const int nx = I.nx, ny = I.ny, nz = I.nz, pitch = I.pitch;
     const int tix = tile % I.tiles_x;
     const int trest = tile / I.tiles_x;
     int tiy, tiz;
@@ -179,7 +180,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
 
     const Planes<real, AUX> hin(pick(I.h, par), I.Np), hout(pick(I.h, par ^ 1), I.Np);
     const Planes<real, AUX, LAUX> gin(pick(I.g, par), I.Np), gout(pick(I.g, par ^ 1), I.Np);
-    const Planes<real, 0, LAUX> pprev(I.phi_prev, N);
+    const Planes<real, 0, LAUX> pprev(I.phi_prev, I.Nm);
     const Planes<fst, AUX, LAUX> fin(pick(I.f, par), I.Np), fout(pick(I.f, par ^ 1), I.Np);
     // node (row + col) of plane a; with ROW the row is wave-uniform
     auto LD = [&](const auto& P, int a, unsigned row, int col) -> real {
@@ -199,7 +200,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     const bool row_ok = y < ny && z < nz;
     const bool valid = row_ok && x < nx;
     const int xv = x < nx ? x : 0;
-    const unsigned rowO = row_ok ? (unsigned)((z * ny + y) * nx) : 0u;  // own row
+    const unsigned rowO = row_ok ? (unsigned)((z * ny + y) * pitch) : 0u;  // own row
     // memory columns of this node for populations with c_x = 0, +1, -1 (x-shifted layout)
     const int xc0 = xv, xcp = xmem(xv, 1, nx), xcm = xmem(xv, -1, nx);
     auto xcol = [&](int cx) { return cx > 0 ? xcp : (cx < 0 ? xcm : xc0); };
@@ -235,7 +236,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             const int by = r % BY, bz = r / BY;
             const int gy = wrap_coord(y0 + by - 1, ny);
             const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
-            const unsigned rb = (unsigned)((gz * ny + gy) * nx);
+            const unsigned rb = (unsigned)((gz * ny + gy) * pitch);
             const int b = r * BX + lx;
             real phi = 0;
 #pragma unroll
@@ -256,7 +257,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             const int by = rj % BY, bz = rj / BY;
             const int gy = wrap_coord(y0 + by - 1, ny);
             const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
-            const unsigned rb = (unsigned)((gz * ny + gy) * nx);
+            const unsigned rb = (unsigned)((gz * ny + gy) * pitch);
             const int b = rj * BX + 64 + (lx & 1);
             real phi = 0;
 #pragma unroll
@@ -277,7 +278,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             const int gx = box_x(bx);
             const int gy = wrap_coord(y0 + by - 1, ny);
             const int gz = (DIM == 3) ? wrap_coord(z0 + bz - 1, nz) : 0;
-            const unsigned rb = (unsigned)((gz * ny + gy) * nx);
+            const unsigned rb = (unsigned)((gz * ny + gy) * pitch);
             real phi = 0;
 #pragma unroll
             for (int a = 0; a < S::Q; a++) {
@@ -318,7 +319,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     auto row = [&](int cy, int cz) -> unsigned {
         const int yy = cy > 0 ? yp : (cy < 0 ? ym : y);
         const int zz = cz > 0 ? zp : (cz < 0 ? zm : z);
-        return (unsigned)((zz * ny + yy) * nx);
+        return (unsigned)((zz * ny + yy) * pitch);
     };
 
     const real psi = s_phi[bo];  // phi + 1
