@@ -22,8 +22,8 @@
  *   - Streams: all device work is enqueued on the HIP stream given at creation (a hipStream_t,
  *     NULL for the null stream). lbcg_step only enqueues; read, write, measure and growth-rate
  *     calls synchronise that stream before returning.
- *   - Layout: scalar fields are [z][y][x] with x fastest; population arrays are planes
- *     [a][z][y][x] in the lattice order
+ *   - Layout (of what the read and write calls take and give): scalar fields are [z][y][x] with
+ *     x fastest; population arrays are planes [a][z][y][x] in the lattice order
  *       D2Q5/D3Q7 : 0, +x, -x, +y, -y, (+z, -z)
  *       D2Q9      : 0, +x, -x, +y, -y, (1,1), (-1,-1), (1,-1), (-1,1)
  *       D3Q19     : 0, +x, -x, +y, -y, +z, -z, (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0),
@@ -139,7 +139,10 @@ typedef struct lbcg_batch lbcg_batch;
 
 /* Bytes of device workspace one solver needs (0 if the parameters are invalid). It holds two
  * copies (ping-pong) of each population array, phi_prev, a staging area for read-back, the
- * reduction scratch, the measurement history of lbcg_run (32 KB) and, with walls, the wall mask. */
+ * reduction scratch, the measurement history of lbcg_run (32 KB) and, with walls, the wall mask.
+ * Inside it, rows are stored at a pitch of nx rounded up to 64 nodes and population planes at a
+ * stride of the stored plane rounded up to 64 nodes plus 64 (nx and N where a binary64 plane
+ * would reach 2^32 bytes); the field and raw-array calls convert to and from the dense layout. */
 size_t lbcg_workspace_bytes(const lbcg_params* p);
 
 /* Validate p, bind the caller's workspace (device pointer, >= lbcg_workspace_bytes bytes,
