@@ -13,7 +13,7 @@ from paper_2206_02145_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-10, "fp32": 1e-4, "fp16shift": 5e-3}
-N_CASES = 16
+N_CASES = 32
 
 
 @pytest.fixture(scope="module")
@@ -92,9 +92,10 @@ def test_random_combination(lb, orc, k):
     rf = ref.fields()
     errs = {k2: relerr(s.read(k2), rf[k2]) for k2 in ("phi", "U", "rho")}
     if p["flow"]:
-        # velocity scale: the flow's, the inflow's, or 1e-9 where nothing drives a flow (u* is then
-        # rounding noise on both sides: 0 on the GPU, ~1e-19 from the oracle's dense MRT solve)
-        um = max([np.abs(rf[c]).max() for c in ("ux", "uy", "uz")] + [p["u_in"], 1e-9])
+        # velocity scale: the flow's, the inflow's, or 1e-6 where nothing drives a flow (a closed or
+        # periodic box without inflow: u* is then rounding noise on both sides, 0 on the GPU and up
+        # to ~1e-17 from the oracle's dense MRT solve; every driven flow here exceeds 5e-3)
+        um = max([np.abs(rf[c]).max() for c in ("ux", "uy", "uz")] + [p["u_in"], 1e-6])
         du = max(float(np.abs(s.read(c) - rf[c]).max()) for c in ("ux", "uy", "uz"))
         errs["u"] = du / um if um > 0 else du
     print(f"[combo]   " + ", ".join(f"{k2}={v:.2e}" for k2, v in errs.items()), flush=True)
