@@ -134,14 +134,15 @@ def test_ragged_and_tiny_grids_pressure_outlet_and_mrt(lb, orc, dim, dims, xbc, 
 # ---- full-size one-step checks in the benchmark's launch configuration ------------------------
 
 FULL_SIZE = {"config2": W.config2, "config3": W.config3,
-             "config3_chmrt": lambda: dict(W.config3(), collision=1, omega_bulk=1.0)}
+             "config3_chmrt": lambda: dict(W.config3(), collision=1, omega_bulk=1.0),
+             "config3_half_source": lambda: dict(W.config3(), solute_source=1)}
 
 
 @pytest.mark.parametrize("cfg", sorted(FULL_SIZE))
 def test_full_size_one_step_from_gpu_state(lb, orc, cfg):
     """Run the full-size grid a while on the GPU (binary32), hand its state to the oracle, and
     check one more step of every node against the oracle's step from the same state (also with the
-    central-Hermite MRT flow collision)."""
+    central-Hermite MRT flow collision and with the half solute source)."""
     p = FULL_SIZE[cfg]()
     print(f"[parity] full-size {cfg} one step", flush=True)
     s = lb.Solver(p, "fp32")
