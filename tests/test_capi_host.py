@@ -138,3 +138,15 @@ def test_largest_grid_is_accepted_and_one_node_more_is_not():
         planes = 2 * (2 * 7) + 1
         assert nb >= planes * (2 ** 29 - 1) * (8 if prec == "fp64" else 4), (prec, nb)
         assert lbcg.lbcg_workspace_bytes(lbcg.make_params(dict(big, nx=2090), prec)) == 0, prec
+
+
+def test_workspace_holds_the_padded_row_pitch():
+    """Rows are stored at a pitch of nx rounded up to 64 nodes and population planes at a stride of
+    the stored plane rounded up to 64 plus 64: a 65-wide grid needs the room of a 128-wide one."""
+    for prec in ("fp64", "fp32"):
+        a = lbcg.lbcg_workspace_bytes(lbcg.make_params(W.params(dim=3, nx=65, ny=20, nz=10, flow=1), prec))
+        b = lbcg.lbcg_workspace_bytes(lbcg.make_params(W.params(dim=3, nx=128, ny=20, nz=10, flow=1), prec))
+        c = lbcg.lbcg_workspace_bytes(lbcg.make_params(W.params(dim=3, nx=64, ny=20, nz=10, flow=1), prec))
+        es = 8 if prec == "fp64" else 4
+        assert a >= (2 * 7 * 2 + 19 * 2 + 1) * 128 * 20 * 10 * es, prec
+        assert c < a and abs(a - b) < 128 * 1024, (prec, a, b, c)  # the dense staging area differs
