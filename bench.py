@@ -467,6 +467,9 @@ def main():
     c3w = gpu_case("3-D flow 192x128x128 fp32, walls and a baffle", pw, "fp32", args.steps, args.warmup, False, mw)
     chm = gpu_case("3-D flow 192x128x128 fp32, central-Hermite MRT", dict(p3, collision=1, omega_bulk=1.0), "fp32",
                    args.steps, args.warmup, False)
+    # rows of 191 nodes (764 B, stored at a pitch of 256 nodes) and planes of a power-of-two size
+    rag = gpu_case("3-D flow 191x128x128 fp32", W.scaled(p3, 191, 128, 128), "fp32", args.steps, args.warmup, False)
+    pw2 = gpu_case("3-D flow 256x128x128 fp32", W.scaled(p3, 256, 128, 128), "fp32", args.steps, args.warmup, False)
     sweep = None if args.no_sweep else sweep_case(args.sweep_n, args.sweep_steps, MEASURE_EVERY)
     surr = None
     if not args.no_surrogate:
@@ -510,6 +513,8 @@ def main():
             "no_flow_128cube": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c2.items()},
             "flow_walls_baffle": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in c3w.items()},
             "flow_chmrt": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in chm.items()},
+            "flow_191_rows": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rag.items()},
+            "flow_256_wide": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in pw2.items()},
         },
     }
     print(json.dumps(rec), flush=True)
