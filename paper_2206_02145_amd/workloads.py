@@ -52,6 +52,14 @@ def config3() -> dict:
                   seed_c=(64, 64, 64), seed_R=12.0)
 
 
+def config3_reduced() -> dict:
+    """The 192x128x128 flow configuration at half size and with a moderate anisotropy: 96x64x64,
+    inlet u 0.02 at x-, outlet x+, periodic y/z, seed R 6 at (32, 32, 32), U0 = U_in = 0.3,
+    eps 0.02 (below 1/35, where the interface stiffness stays positive), 20000 steps."""
+    return params(dim=3, nx=96, ny=64, nz=64, flow=1, xbc=1, u_in=0.02, U0=0.3, U_in=0.3,
+                  seed_c=(32, 32, 32), seed_R=6.0, eps=0.02)
+
+
 def scaled(p: dict, nx: int, ny: int, nz: int = 1, seed_R: float | None = None) -> dict:
     """The same physics on a smaller grid, the seed kept at the same relative position."""
     q = dict(p)

@@ -4,6 +4,8 @@ the full-length parity test of the GPU path.
     python tests/golden/make_fulllength.py c2     # 128^3 without flow, 5000 steps (minutes)
     python tests/golden/make_fulllength.py c3     # 192x128x128 with flow, 20000 steps (hours);
                                                   # also a snapshot after 4000 steps
+    python tests/golden/make_fulllength.py c3r    # 96x64x64 with flow at eps 0.02, 20000 steps,
+                                                  # snapshots every 4000 steps (tens of minutes)
 
 Only the oracle (binary64, OpenMP over the host's cores) and the seeded workload definitions are
 used. Stored per field (phi, U, and rho, ux, uy, uz with flow): the values on the planes z = nz/2
@@ -26,7 +28,8 @@ from oracle import oracle as O  # noqa: E402
 from paper_2206_02145_amd import workloads as W  # noqa: E402
 
 # configuration, step count, earlier snapshots (files fulllength_<case>_<steps>.npz)
-CASES = {"c2": (W.config2, 5000, ()), "c3": (W.config3, 20000, (4000,))}
+CASES = {"c2": (W.config2, 5000, ()), "c3": (W.config3, 20000, (4000,)),
+         "c3r": (W.config3_reduced, 20000, (4000, 8000, 12000, 16000))}
 N_RANDOM = 8192
 
 

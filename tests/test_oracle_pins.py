@@ -102,6 +102,87 @@ def test_aniso_threshold_and_symmetry(orc):
 
 
 # --------------------------------------------------------------------------------------------
+# The anisotropy flux of Eq. (e) inside the phase-field collision (Section 2.2, phase-field
+# paragraph; R4, R5, R6): its first moment on a non-uniform field whose gradient is known exactly
+# --------------------------------------------------------------------------------------------
+
+def n_fd(eps, p):
+    """N = |p|^2 d(a_s^2)/dp (the flux of Eq. (a)) by central differences of the trigonometric a_s."""
+    s = float(np.dot(p, p))
+    hstep = 1e-5 * math.sqrt(s)
+    grad = np.zeros(3)
+    for d in range(3):
+        e = np.zeros(3)
+        e[d] = hstep
+        grad[d] = (a_trig(eps, p + e) ** 2 - a_trig(eps, p - e) ** 2) / (2 * hstep)
+    return s * grad
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_phase_field_flux_first_moment(orc, dim):
+    """On a quadratic phi the isotropic central gradient is exact, so grad phi, a_s, tau_phi and the
+    flux N = |grad phi|^2 d(a_s^2)/d(grad phi) are known in closed form at every interior node.
+    Eq. (e)'s equilibrium h_eq = w (phi - (1/cs^2) c.N W0^2/tau0) has first moment -(W0^2/tau0) N
+    (sum w c c = cs^2 I), and the source w Q/tau0 has none, so the post-collision populations,
+    recovered from the new ones by inverting Eq. (d) at the collision node (R6),
+        h*_a(x) = a_s^2(x) h'_a(x + c_a) + (1 - a_s^2(x)) h_a(x + c_a),
+    must satisfy sum_a c_a h*_a = (1 - 1/tau_phi) sum_a c_a h_a - (W0^2/tau0) N / tau_phi,
+    with sum_a h*_a = phi + Q/tau0. A flux of the wrong size (half of it, or the gradient without
+    its 1/cs^2) or sign fails this."""
+    n = 20 if dim == 2 else 14
+    nz = 1 if dim == 2 else n
+    eps = 0.05
+    p = W.params(dim=dim, nx=n, ny=n, nz=nz, flow=0, xbc=0, eps=eps, U0=0.1, U_in=0.1, seed_R=-1e9)
+    s = orc.Sim(p, init=False)
+    c, w, cs2 = orc.lattice(0 if dim == 2 else 1)
+    k = p["W0"] ** 2 / p["tau0"]
+    rng = np.random.default_rng(11 + dim)
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(n), np.arange(n), indexing="ij")
+    r = np.stack([X, Y, Z], -1).astype(float) - np.array([n / 2, n / 2, nz / 2 if dim == 3 else 0])
+    b = np.array([0.031, -0.047, 0.023 if dim == 3 else 0.0])
+    M = rng.normal(size=(3, 3)) * 0.004
+    M = M + M.T
+    if dim == 2:
+        M[2, :] = M[:, 2] = 0.0
+    phi = 0.1 + r @ b + 0.5 * np.einsum("...i,ij,...j->...", r, M, r)
+    grad = b + r @ M
+    # a non-equilibrium distribution with sum phi (random parts of zero sum)
+    dev = rng.normal(size=(len(w),) + phi.shape) * 0.01
+    dev -= dev.mean(0)
+    s.h[:] = w[:, None, None, None] * phi[None] + dev
+    s.g[:] = w[:, None, None, None] * 0.1
+    s.phi_prev[:] = phi
+    h0 = s.h.copy()
+    U = s.g.sum(0)
+    s.step(1)
+    h1 = s.h
+    checked = 0
+    lo, hi = 2, n - 2
+    for z in (range(2, nz - 2) if dim == 3 else (0,)):
+        for y in range(lo, hi):
+            for x in range(lo, hi):
+                pg = grad[z, y, x]
+                a = a_trig(eps, pg)
+                N = n_fd(eps, pg)
+                tau = a * a * k / cs2 + 0.5
+                hs = np.zeros(len(w))
+                for al in range(len(w)):
+                    xd, yd, zd = x + c[al, 0], y + c[al, 1], z + c[al, 2]
+                    hs[al] = a * a * h1[al, zd, yd, xd] + (1 - a * a) * h0[al, zd, yd, xd]
+                ph = h0[:, z, y, x].sum()
+                Q = ph - ph ** 3 + p["lam"] * U[z, y, x] * (1 - ph ** 2) ** 2
+                assert abs(hs.sum() - (ph + Q / p["tau0"])) < 1e-13
+                j0 = (c * h0[:, z, y, x][:, None]).sum(0)
+                j1 = (c * hs[:, None]).sum(0)
+                expect = (1 - 1 / tau) * j0 - k * N / tau
+                assert np.abs(j1 - expect).max() < 1e-9 * max(1.0, np.abs(k * N).max() / 1e-3), \
+                    (x, y, z, j1, expect)
+                assert np.abs(k * N).max() > 1e-5 or abs(a - 1) < 1e-3
+                checked += 1
+    assert checked >= (64 if dim == 2 else 300)
+
+
+# --------------------------------------------------------------------------------------------
 # Single node: collision moment identities (P-a); streaming is the identity on a 1-node grid
 # --------------------------------------------------------------------------------------------
 
@@ -436,6 +517,73 @@ def test_plug_flow_is_steady_and_attracting(orc):
     fl = s.fields()
     assert np.abs(fl["rho"] * fl["ux"] - 0.02).max() < 1e-8
     assert np.ptp(fl["rho"]) < 1e-9 and np.abs(fl["uy"]).max() < 1e-12
+
+
+def test_outlet_is_zero_gradient_extrapolation(orc):
+    """The outlet (R15) continues the field past x = nx-1 with zero gradient: the population that
+    enters the outlet node from outside is the one a ghost node at x = nx, holding the state of
+    x = nx-1, would have sent. With relaxation times of exactly 1 the post-collision populations are
+    the equilibria of the node's own moments, so after one step every unknown population at the
+    outlet is known in closed form: g_a = w_a U (1 + c_a.u/cs^2) and f_a = f_eq,a(rho, u) of the
+    node (nx-1, y - c_ay), and h_a = w_a (phi + Q/tau0) with eps = 0. The fields vary along x, so a
+    copy from elsewhere (x = nx-3, or an average of columns) fails this."""
+    nx, ny = 12, 6
+    rng = np.random.default_rng(5)
+    # flow and solute: phi = -1 everywhere (no drag, q = 2), tau_U = 2 D/cs2 + 1/2 = 1, tau_f = 1
+    p = W.params(dim=2, nx=nx, ny=ny, flow=1, xbc=1, u_in=0.01, U0=0.2, U_in=0.2, seed_R=-1e9,
+                 D=1 / 12, nu=1 / 6)
+    s = orc.Sim(p, init=False)
+    cs_, ws, cs2s = orc.lattice(0)
+    cf, wf, cs2f = orc.lattice(2)
+    s.h[:] = -ws[:, None, None, None]
+    s.phi_prev[:] = -1.0
+    U = 0.2 + 0.1 * rng.uniform(size=(1, ny, nx))
+    rho = 1 + 0.02 * rng.uniform(-1, 1, size=(1, ny, nx))
+    ux = 0.02 * rng.uniform(-1, 1, size=(1, ny, nx))
+    uy = 0.02 * rng.uniform(-1, 1, size=(1, ny, nx))
+
+    def feq(a, r, vx, vy):
+        cu = (cf[a, 0] * vx + cf[a, 1] * vy) / cs2f
+        return wf[a] * r * (1 + cu + 0.5 * cu * cu - (vx * vx + vy * vy) / (2 * cs2f))
+
+    for a in range(9):  # equilibrium plus a non-equilibrium part with no mass or momentum
+        s.f[a] = feq(a, rho, ux, uy)
+    noise = rng.normal(size=(9, 1, ny, nx)) * 1e-3 * wf[:, None, None, None]
+    # remove the mass and momentum of the noise so that rho and u stay as drawn
+    A = np.stack([np.ones(9), cf[:, 0], cf[:, 1]])
+    P = np.eye(9) - A.T @ np.linalg.solve(A @ A.T, A)
+    s.f += np.einsum("ab,b...->a...", P, noise)
+    s.g[:] = ws[:, None, None, None] * U + np.einsum("ab,b...->a...",
+                                                    np.eye(5) - np.outer(np.ones(5), np.ones(5)) / 5,
+                                                    rng.normal(size=(5, 1, ny, nx)) * 1e-3)
+    U = s.g.sum(0)
+    s.step(1)
+    x = nx - 1
+    for y in range(ny):
+        for a in range(5):
+            if cs_[a, 0] < 0:
+                expect = ws[a] * U[0, y, x] * (1 + (cs_[a, 0] * ux[0, y, x] + cs_[a, 1] * uy[0, y, x]) / cs2s)
+                assert abs(s.g[a, 0, y, x] - expect) < 1e-15, ("g", a, y)
+        for a in range(9):
+            if cf[a, 0] < 0:
+                ys = (y - cf[a, 1]) % ny
+                expect = feq(a, rho[0, ys, x], ux[0, ys, x], uy[0, ys, x])
+                assert abs(s.f[a, 0, y, x] - expect) < 1e-15, ("f", a, y)
+
+    # phase field: no flow, eps = 0 and W0^2/tau0 = cs2/2 give tau_phi = 1; lambda = 0
+    p = W.params(dim=2, nx=nx, ny=ny, flow=0, xbc=1, U0=0.2, U_in=0.2, seed_R=-1e9, eps=0.0,
+                 lam=0.0, W0=1.0, tau0=6.0)
+    s = orc.Sim(p, init=False)
+    phi = rng.uniform(-0.9, 0.9, size=(1, ny, nx))
+    dev = rng.normal(size=(5, 1, ny, nx)) * 1e-3
+    s.h[:] = ws[:, None, None, None] * phi + dev - dev.mean(0)
+    s.g[:] = ws[:, None, None, None] * 0.2
+    s.phi_prev[:] = phi
+    s.step(1)
+    for y in range(ny):
+        ph = phi[0, y, nx - 1]
+        expect = ws[2] * (ph + (ph - ph ** 3) / 6.0)
+        assert abs(s.h[2, 0, y, nx - 1] - expect) < 1e-15, ("h", y)
 
 
 @pytest.mark.parametrize("dim", [2, 3])
