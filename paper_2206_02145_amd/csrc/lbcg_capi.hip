@@ -738,7 +738,8 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
                    p->flow ? p->u_inlet : 0.0, p->seed_tilt, p->seed_shape};
         // unused halves of the ping-pong buffers start defined (zero) so raw reads are reproducible
         HIPCHK(hipMemsetAsync(hdl->ws, 0, L.staging, hdl->stream));
-        if (p->walls) HIPCHK(hipMemsetAsync(hdl->ws + L.wall, 0, (size_t)hdl->inst.N, hdl->stream));
+        // the whole mask region, pad columns of the stored rows included (the mask starts empty)
+        if (p->walls) HIPCHK(hipMemsetAsync(hdl->ws + L.wall, 0, stored_nodes(p), hdl->stream));
         hdl->ops->init(hdl->inst, 0, a, hdl->stream);
         HIPCHK(hipGetLastError());
     });

@@ -151,7 +151,9 @@ def _dptr(a):
 class Solver:
     """One grid: owns a torch device workspace and a library handle."""
 
-    def __init__(self, p: dict, precision: str = "fp32", stream=None):
+    def __init__(self, p: dict, precision: str = "fp32", stream=None, ws_fill: int | None = None):
+        """ws_fill: if given, the byte every workspace byte holds before lbcg_create (the library
+        must not depend on the workspace's prior contents)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("the lbcg solver needs a HIP device")
@@ -163,7 +165,11 @@ class Solver:
             # reproduce the validation error message through lbcg_create
             h = ctypes.c_void_p()
             check(lib().lbcg_create(ctypes.byref(self.params), None, 0, None, ctypes.byref(h)), "lbcg_create")
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        if ws_fill is None:
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        else:
+            self.ws = torch.full((nbytes,), int(ws_fill), dtype=torch.uint8, device="cuda")
+            torch.cuda.synchronize()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.handle = ctypes.c_void_p()
         check(lib().lbcg_create(ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
@@ -400,7 +406,11 @@ class MLP:
         nbytes = int(lib().lbcg_mlp_workspace_bytes(self.nl, self._w, self.max_batch))
         if nbytes == 0:
             raise ValueError("invalid MLP shape")
-        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        if ws_fill is None:
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        else:
+            self.ws = torch.full((nbytes,), int(ws_fill), dtype=torch.uint8, device="cuda")
+            torch.cuda.synchronize()
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.handle = ctypes.c_void_p()
         check(lib().lbcg_mlp_create(self.nl, self._w, self.max_batch, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
