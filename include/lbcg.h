@@ -223,7 +223,8 @@ lbcg_status lbcg_variant_time(lbcg_handle* h, int idx, int launches, double* us)
 
 /* Time every variant as lbcg_variant_time does, select the fastest, and return its index and
  * time (either output may be NULL). The state advances by (launches + 1) x lbcg_variant_count
- * steps. Synchronises. */
+ * steps. The choice is recorded in the process's tuning cache (see lbcg_batch_autotune), so later
+ * solvers of the same grid kind, shape, precision and architecture start with it. Synchronises. */
 lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_us);
 
 /* ---- Checkpoints ----
@@ -297,6 +298,30 @@ lbcg_status lbcg_batch_read_field(lbcg_batch* b, int inst, int field, void* dst,
 
 int64_t lbcg_batch_step_count(const lbcg_batch* b);  /* -1 for NULL */
 
+/* Batch tilings and their autotuner (the sweeps of Sections 4.1.3, 4.1.4 and 4.2 as one launch per
+ * step). A batch can run its step kernel in several tilings (tile shapes and cache policies, the
+ * first the default); every tiling computes what the single-grid kernel of the same tiling computes.
+ * lbcg_batch_variant_time times real batched steps with tiling idx (HIP events on the batch's stream:
+ * one untimed step, then `launches` timed ones, the ping-pong copies alternating), so the state
+ * advances by launches + 1 steps; the selected tiling is left as it was. lbcg_batch_autotune times
+ * every tiling that way (all_us[count] receives each time, may be NULL), selects the fastest and
+ * records the choice in the process's tuning cache under the kernel kind, precision, GPU
+ * architecture and the batch's mix of instance shapes; lbcg_batch_create then starts every batch
+ * with the same key on that tiling. With the environment variable LBCG_TUNE_CACHE naming a file,
+ * the cache is also read from it at first use and every choice is appended to it. lbcg_autotune
+ * records its choice for single grids in the same cache (key: kernel kind, grid shape, precision,
+ * architecture), which lbcg_create applies. Selecting a tiling synchronises the stream and drops
+ * the batch's captured graphs. */
+int lbcg_batch_variant_count(const lbcg_batch* b);   /* -1 for NULL */
+int lbcg_batch_variant_current(const lbcg_batch* b); /* -1 for NULL */
+lbcg_status lbcg_batch_variant_name(const lbcg_batch* b, int idx, char* buf, size_t buflen);
+lbcg_status lbcg_batch_variant_select(lbcg_batch* b, int idx);
+lbcg_status lbcg_batch_variant_time(lbcg_batch* b, int idx, int launches, double* us);
+lbcg_status lbcg_batch_autotune(lbcg_batch* b, int launches, int* best, double* best_us, double* all_us);
+/* Forget every choice of the tuning cache in this process (the cache file is not touched or read
+ * again). */
+lbcg_status lbcg_tune_cache_clear(void);
+
 /* Release the host state and captured graphs (the workspace stays the caller's). NULL accepted. */
 lbcg_status lbcg_batch_destroy(lbcg_batch* b);
 
@@ -333,6 +358,10 @@ lbcg_status lbcg_mlp_destroy(lbcg_mlp* m);
 
 /* Message of the calling thread's last error ("" if none). */
 const char* lbcg_last_error(void);
+
+/* Digest of the sources the library was built from (the build stores it; "unknown" if it did not),
+ * so that a caller can refuse a library older than its sources. */
+const char* lbcg_source_hash(void);
 
 #ifdef __cplusplus
 }

@@ -222,7 +222,7 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_kernel(InstDev I, int par,
 // partials of blocks l, l + 64, l + 128, ... in that order, then lane k combines value k of the 64
 // lane sums in lane order. (One lane walking all partials in order waits on one dependent load per
 // block: ~150 us for 1024 blocks.)
-__global__ __launch_bounds__(64) void reduce_final(const double* partials, int nblocks, double* out) {
+static __global__ __launch_bounds__(64) void reduce_final(const double* partials, int nblocks, double* out) {
     __shared__ double s[RED_VALUES][64];
     const int l = threadIdx.x;
     double v[RED_VALUES];

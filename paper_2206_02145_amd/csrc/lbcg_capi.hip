@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <type_traits>
@@ -18,6 +20,7 @@
 #include "../../include/lbcg.h"
 #include "diag.hpp"
 #include "errors.hpp"
+#include "kits.hpp"
 #include "lattice.hpp"
 #include "march.hpp"
 #include "step.hpp"
@@ -153,17 +156,6 @@ Layout layout_of(const lbcg_params* p) {
     return L;
 }
 
-// Tiling of the step kernel: a TX x TY x TZ block, or (march) TY full rows x TZ planes.
-struct Tiling {
-    bool march;
-    int TX, TY, TZ;
-    bool prefetch;  // own populations loaded before the halo barrier
-    int aux;        // store cache policy
-    int laux = 0;   // cache policy of the single-use loads (g, f, phi_prev)
-    int zband = 0;  // z tile-layers per band of the block tile order (0: plain x, y, z order)
-    bool walls = false;  // the kernel honours the solid-wall mask
-    bool chm = false;    // central-Hermite MRT flow collision
-};
 
 InstDev make_inst(const lbcg_params* p, char* ws, const Layout& L, const Tiling& T) {
     InstDev I{};
@@ -549,52 +541,7 @@ int storage_kind(const lbcg_params& p, int field) {  // 0 double, 1 float, 2 hal
 }
 
 
-// ---- batched launches (many independent grids of one kind) ----
-struct BatchKit {
-    Tiling tiling;
-    void (*step)(const InstDev* d, int n, int tiles, int par, hipStream_t);
-    void (*ray)(const InstDev* d, int n, int par, const double* dirs, int ndirs, const double* centers,
-                double* out, hipStream_t);
-};
-
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, bool CHM = false>
-struct BatchImpl {
-    static void step(const InstDev* d, int n, int tiles, int par, hipStream_t s) {
-        hipLaunchKernelGGL((step_batch<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, 0, CHM>), dim3(tiles),
-                           dim3(TX * TY * TZ), 0, s, d, n, par);
-    }
-    static void ray(const InstDev* d, int n, int par, const double* dirs, int ndirs, const double* centers,
-                    double* out, hipStream_t s) {
-        hipLaunchKernelGGL((raymarch_batch_kernel<DIM, real>), dim3(ndirs, n), dim3(64), 0, s, d, par, dirs, ndirs,
-                           centers, out);
-    }
-    static BatchKit kit() {
-        Tiling t{false, TX, TY, TZ, PF, AUX, 0, 0};
-        t.chm = CHM;
-        return BatchKit{t, step, ray};
-    }
-};
-
-// kind: 0 no flow, 1 BGK flow, 2 central-Hermite MRT flow
-const BatchKit& batch_kit_for(int dim, int kind, int prec) {
-    static const BatchKit k2[3][3] = {
-        {BatchImpl<2, false, double, double, 64, 4, 1, false, 0>::kit(), BatchImpl<2, false, float, float, 64, 4, 1, false, 2>::kit(),
-         BatchImpl<2, false, float, float, 64, 4, 1, false, 2>::kit()},
-        {BatchImpl<2, true, double, double, 64, 4, 1, false, 0>::kit(), BatchImpl<2, true, float, float, 64, 4, 1, false, 2>::kit(),
-         BatchImpl<2, true, float, __half, 64, 4, 1, false, 2>::kit()},
-        {BatchImpl<2, true, double, double, 64, 4, 1, false, 0, true>::kit(),
-         BatchImpl<2, true, float, float, 64, 4, 1, false, 2, true>::kit(),
-         BatchImpl<2, true, float, __half, 64, 4, 1, false, 2, true>::kit()}};
-    static const BatchKit k3[3][3] = {
-        {BatchImpl<3, false, double, double, 16, 4, 4, false, 0>::kit(), BatchImpl<3, false, float, float, 64, 2, 4, false, 2>::kit(),
-         BatchImpl<3, false, float, float, 64, 2, 4, false, 2>::kit()},
-        {BatchImpl<3, true, double, double, 16, 4, 4, false, 0>::kit(), BatchImpl<3, true, float, float, 64, 2, 4, false, 2>::kit(),
-         BatchImpl<3, true, float, __half, 64, 2, 4, false, 2>::kit()},
-        {BatchImpl<3, true, double, double, 16, 4, 4, false, 0, true>::kit(),
-         BatchImpl<3, true, float, float, 64, 2, 4, false, 2, true>::kit(),
-         BatchImpl<3, true, float, __half, 64, 2, 4, false, 2, true>::kit()}};
-    return dim == 2 ? k2[kind][prec] : k3[kind][prec];
-}
+// ---- batched launches (many independent grids of one kind; kernels in batch_kits.hip) ----
 
 // Per-instance population buffers inside a batch workspace (the single-grid layout without its
 // staging and diagnostics areas).
@@ -655,6 +602,108 @@ void validate_batch(int n, const lbcg_params* p) {
     if (tiles > (1LL << 31)) throw Error(LBCG_EINVAL, "batch too large");
 }
 
+// ---- autotuning cache ----
+// The tiling the autotuner found fastest, keyed by the kernel kind, the grid shape (or a batch's
+// mix of shapes), the precision and the GPU architecture, stored by name. Kept for the life of the
+// process; with the environment variable LBCG_TUNE_CACHE naming a file, also read from that file at
+// first use and appended to after each tuning (one "key<TAB>tiling" line per choice).
+struct TuneCache {
+    std::mutex mu;
+    bool loaded = false;
+    std::map<std::string, std::string> m;
+};
+TuneCache& tune_cache() {
+    static TuneCache c;
+    return c;
+}
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    const std::string a = prop.gcnArchName;
+    return a.substr(0, a.find(':'));
+}
+
+void tune_load_locked(TuneCache& c) {
+    if (c.loaded) return;
+    c.loaded = true;
+    const char* path = std::getenv("LBCG_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[4096];
+    while (std::fgets(line, sizeof line, f)) {
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        const size_t t = l.find('\t');
+        if (t != std::string::npos) c.m[l.substr(0, t)] = l.substr(t + 1);
+    }
+    std::fclose(f);
+}
+
+bool tune_lookup(const std::string& key, std::string& name) {
+    TuneCache& c = tune_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    tune_load_locked(c);
+    auto it = c.m.find(key);
+    if (it == c.m.end()) return false;
+    name = it->second;
+    return true;
+}
+
+void tune_store(const std::string& key, const std::string& name) {
+    TuneCache& c = tune_cache();
+    std::lock_guard<std::mutex> lock(c.mu);
+    tune_load_locked(c);
+    c.m[key] = name;
+    const char* path = std::getenv("LBCG_TUNE_CACHE");
+    if (path && *path) {
+        if (std::FILE* f = std::fopen(path, "a")) {
+            std::fprintf(f, "%s\t%s\n", key.c_str(), name.c_str());
+            std::fclose(f);
+        }
+    }
+}
+
+// Key of a single grid: kernel kind, shape, precision, architecture.
+std::string grid_key(const lbcg_params& p) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "grid %s dim=%d flow=%d prec=%d xbc=%d walls=%d coll=%d %dx%dx%d",
+                  arch_name().c_str(), p.dim, p.flow, p.precision, p.xbc, p.walls, p.collision, p.nx, p.ny, p.nz);
+    return buf;
+}
+
+// Key of a batch: kernel kind, precision, architecture and the mix of instance shapes (each distinct
+// nx x ny x nz with its x-face kind and count; a 64-bit FNV-1a digest of that list if it is long).
+std::string batch_key(int n, const lbcg_params* p) {
+    std::map<std::string, int> mix;
+    for (int i = 0; i < n; i++) {
+        char b[96];
+        std::snprintf(b, sizeof b, "%dx%dx%d/%d", p[i].nx, p[i].ny, p[i].nz, p[i].xbc);
+        mix[b]++;
+    }
+    std::string m;
+    for (const auto& kv : mix) m += kv.first + "*" + std::to_string(kv.second) + ",";
+    if (m.size() > 400) {
+        unsigned long long hsh = 1469598103934665603ull;
+        for (unsigned char ch : m) hsh = (hsh ^ ch) * 1099511628211ull;
+        char b[40];
+        std::snprintf(b, sizeof b, "fnv:%016llx", hsh);
+        m = b;
+    }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "batch %s dim=%d flow=%d prec=%d coll=%d n=%d ", arch_name().c_str(), p[0].dim,
+                  p[0].flow, p[0].precision, p[0].collision, n);
+    return buf + m;
+}
+
+int variant_index_by_name(const std::vector<Variant>& v, const std::string& name) {
+    for (int i = 0; i < (int)v.size(); i++)
+        if (variant_name(v[i]) == name) return i;
+    return -1;
+}
+
 }  // namespace
 
 struct lbcg_batch {
@@ -664,7 +713,9 @@ struct lbcg_batch {
     BatchLayout L;
     char* ws;
     hipStream_t stream;
-    const BatchKit* kit;
+    const std::vector<BatchKit>* kits;  // candidate tilings of the batched step
+    int kit_idx;
+    const BatchKit* kit;                // the selected one
     const Ops* common;  // init / field kernels of the instance kind
     int total_tiles;
     int par;
@@ -727,8 +778,10 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
                                      (p->xbc == LBCG_INFLOW_PRESSURE || chm) ? 0 : p->nx,  // (0: no z-marching tiling)
                                      population_bytes(*p), p->walls != 0, chm);
         hdl->variant = 0;
-        hdl->ops = hdl->variants[0].ops;
-        hdl->inst = make_inst(p, hdl->ws, L, hdl->variants[0].tiling);
+        std::string tuned;  // a tiling the autotuner chose for this grid earlier in the process
+        if (tune_lookup(grid_key(*p), tuned)) hdl->variant = std::max(0, variant_index_by_name(hdl->variants, tuned));
+        hdl->ops = hdl->variants[hdl->variant].ops;
+        hdl->inst = make_inst(p, hdl->ws, L, hdl->variants[hdl->variant].tiling);
         hdl->par = 0;
         hdl->nstep = 0;
         hdl->red_blocks = grid_for(hdl->inst.N, RED_THREADS, RED_BLOCKS);
@@ -872,6 +925,37 @@ void write_field_impl(const lbcg_params& p, const InstDev& I, int par, void* sta
     HIPCHK(hipStreamSynchronize(stream));
 }
 
+// The diagnostics of lbcg_measure with their device scratch at `part` (block partials, then the
+// final values), `ddirs` (the directions) and `dout` (the extents, after RED_VALUES slots).
+// Returns true if a non-finite value was found (and marks the handle).
+bool measure_into(lbcg_handle* h, int ndirs, const double* dirs, double* L_out, double* mass_out, double* part,
+                  double* ddirs, double* dout) {
+    check_dirs(h, ndirs, dirs);
+    if (ndirs > 0 && !L_out) throw Error(LBCG_EINVAL, "L_out is required when ndirs > 0");
+    h->ops->reduce(h->inst, h->par, part, h->red_blocks, part + h->red_blocks * RED_VALUES, h->stream);
+    HIPCHK(hipGetLastError());
+    if (ndirs > 0) {
+        HIPCHK(hipMemcpyAsync(ddirs, dirs, sizeof(double) * 3 * ndirs, hipMemcpyHostToDevice, h->stream));
+        h->ops->ray(h->inst, h->par, ddirs, ndirs, h->p.seed_center, dout + RED_VALUES, h->stream);
+        HIPCHK(hipGetLastError());
+    }
+    double host[RED_VALUES + MAX_DIRS];
+    HIPCHK(hipMemcpyAsync(host, part + h->red_blocks * RED_VALUES, sizeof(double) * RED_VALUES,
+                          hipMemcpyDeviceToHost, h->stream));
+    if (ndirs > 0)
+        HIPCHK(hipMemcpyAsync(host + RED_VALUES, dout + RED_VALUES, sizeof(double) * ndirs, hipMemcpyDeviceToHost,
+                              h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (mass_out) std::memcpy(mass_out, host, sizeof(double) * RED_VALUES);
+    if (ndirs > 0) std::memcpy(L_out, host + RED_VALUES, sizeof(double) * ndirs);
+    record_history(h, (double)h->nstep, ndirs, host + RED_VALUES);
+    if (host[5] > 0) {
+        h->nonfinite = true;
+        return true;
+    }
+    return false;
+}
+
 }  // namespace
 
 extern "C" {
@@ -898,32 +982,8 @@ lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* 
     bool nonfinite = false;
     lbcg_status st = guarded([&] {
         if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
-        check_dirs(h, ndirs, dirs);
-        if (ndirs > 0 && !L_out) throw Error(LBCG_EINVAL, "L_out is required when ndirs > 0");
-        double* part = (double*)(h->ws + h->L.partials);
-        double* ddirs = (double*)(h->ws + h->L.dirs);
-        double* dout = (double*)(h->ws + h->L.out);
-        h->ops->reduce(h->inst, h->par, part, h->red_blocks, part + h->red_blocks * RED_VALUES, h->stream);
-        HIPCHK(hipGetLastError());
-        if (ndirs > 0) {
-            HIPCHK(hipMemcpyAsync(ddirs, dirs, sizeof(double) * 3 * ndirs, hipMemcpyHostToDevice, h->stream));
-            h->ops->ray(h->inst, h->par, ddirs, ndirs, h->p.seed_center, dout + RED_VALUES, h->stream);
-            HIPCHK(hipGetLastError());
-        }
-        double host[RED_VALUES + MAX_DIRS];
-        HIPCHK(hipMemcpyAsync(host, part + h->red_blocks * RED_VALUES, sizeof(double) * RED_VALUES,
-                              hipMemcpyDeviceToHost, h->stream));
-        if (ndirs > 0)
-            HIPCHK(hipMemcpyAsync(host + RED_VALUES, dout + RED_VALUES, sizeof(double) * ndirs, hipMemcpyDeviceToHost,
-                                  h->stream));
-        HIPCHK(hipStreamSynchronize(h->stream));
-        if (mass_out) std::memcpy(mass_out, host, sizeof(double) * RED_VALUES);
-        if (ndirs > 0) std::memcpy(L_out, host + RED_VALUES, sizeof(double) * ndirs);
-        record_history(h, (double)h->nstep, ndirs, host + RED_VALUES);
-        if (host[5] > 0) {
-            h->nonfinite = true;
-            nonfinite = true;
-        }
+        nonfinite = measure_into(h, ndirs, dirs, L_out, mass_out, (double*)(h->ws + h->L.partials),
+                                 (double*)(h->ws + h->L.dirs), (double*)(h->ws + h->L.out));
     });
     if (st == LBCG_OK && nonfinite) {
         lbcg::last_error_slot() = "non-finite phi, U or rho found";
@@ -1112,6 +1172,7 @@ lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_
             }
         }
         select_variant(h, bi);
+        tune_store(grid_key(h->p), variant_name(h->variants[bi]));
         if (best) *best = bi;
         if (best_us) *best_us = bt;
     });
@@ -1286,7 +1347,13 @@ lbcg_status lbcg_batch_create(int n, const lbcg_params* p, void* dev_workspace, 
         b->ws = (char*)dev_workspace;
         b->stream = (hipStream_t)hip_stream;
         const int kind = p[0].flow ? (p[0].collision == LBCG_COLLISION_CHMRT ? 2 : 1) : 0;
-        b->kit = &batch_kit_for(p[0].dim, kind, p[0].precision);
+        b->kits = &batch_kits_for(p[0].dim, kind, p[0].precision);
+        b->kit_idx = 0;
+        std::string tuned;  // a tiling the autotuner chose for this mix of instances earlier in the process
+        if (tune_lookup(batch_key(n, p), tuned))
+            for (int k = 0; k < (int)b->kits->size(); k++)
+                if (variant_name(Variant{nullptr, (*b->kits)[k].tiling}) == tuned) b->kit_idx = k;
+        b->kit = &(*b->kits)[b->kit_idx];
         b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0, false, false)[0].ops;
         b->par = 0;
         b->nstep = 0;
@@ -1419,6 +1486,125 @@ lbcg_status lbcg_batch_read_field(lbcg_batch* b, int inst, int field, void* dst,
 
 int64_t lbcg_batch_step_count(const lbcg_batch* b) { return b ? b->nstep : -1; }
 
+}  // extern "C"
+
+namespace {
+std::string batch_variant_name(const lbcg_batch* b, int idx) {
+    return variant_name(Variant{nullptr, (*b->kits)[idx].tiling});
+}
+
+// Switch the batched step to tiling idx: the instances' tile lists change with the tiling, so the
+// table is rebuilt and uploaded (after the kernels already enqueued, which read it, have run) and
+// the captured graphs are dropped.
+void batch_select(lbcg_batch* b, int idx) {
+    if (idx < 0 || idx >= (int)b->kits->size()) throw Error(LBCG_EINVAL, "variant index out of range");
+    if (idx == b->kit_idx) return;
+    const BatchKit* k = &(*b->kits)[idx];
+    int tiles = 0;
+    for (int i = 0; i < b->n; i++) {
+        InstDev I = make_inst(&b->p[i], b->ws, b->L.inst[i], k->tiling);
+        I.tile_begin = tiles;
+        tiles += I.tiles_x * I.tiles_y * I.tiles_z;
+        b->inst[i] = I;
+    }
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipMemcpyAsync(b->ws + b->L.table, b->inst.data(), sizeof(InstDev) * b->n, hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    for (auto& g : b->graphs) HIPCHK(hipGraphExecDestroy(g.exec));
+    b->graphs.clear();
+    b->kit = k;
+    b->kit_idx = idx;
+    b->total_tiles = tiles;
+}
+
+// Mean time per batched step (microseconds) of `launches` steps with tiling idx after one untimed
+// step; real steps, alternating the ping-pong copies as lbcg_batch_run does. The state advances by
+// launches + 1 steps; the selected tiling is left as it was.
+double batch_time_variant(lbcg_batch* b, int idx, int launches) {
+    const int keep = b->kit_idx;
+    batch_select(b, idx);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    batch_chunk(b, b->par, 1, 0);
+    b->par ^= 1;
+    HIPCHK(hipEventRecord(e0, b->stream));
+    batch_chunk(b, b->par, launches, 0);
+    if (launches & 1) b->par ^= 1;
+    HIPCHK(hipEventRecord(e1, b->stream));
+    b->nstep += launches + 1;
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    batch_select(b, keep);
+    return 1e3 * (double)ms / launches;
+}
+}  // namespace
+
+extern "C" {
+
+int lbcg_batch_variant_count(const lbcg_batch* b) { return b ? (int)b->kits->size() : -1; }
+
+int lbcg_batch_variant_current(const lbcg_batch* b) { return b ? b->kit_idx : -1; }
+
+lbcg_status lbcg_batch_variant_name(const lbcg_batch* b, int idx, char* buf, size_t buflen) {
+    return guarded([&] {
+        if (!b || !buf || buflen == 0) throw Error(LBCG_EINVAL, "NULL batch or buffer");
+        if (idx < 0 || idx >= (int)b->kits->size()) throw Error(LBCG_EINVAL, "variant index out of range");
+        std::snprintf(buf, buflen, "%s", batch_variant_name(b, idx).c_str());
+    });
+}
+
+lbcg_status lbcg_batch_variant_select(lbcg_batch* b, int idx) {
+    return guarded([&] {
+        if (!b) throw Error(LBCG_EINVAL, "batch is NULL");
+        batch_select(b, idx);
+    });
+}
+
+lbcg_status lbcg_batch_variant_time(lbcg_batch* b, int idx, int launches, double* us) {
+    return guarded([&] {
+        if (!b || !us) throw Error(LBCG_EINVAL, "NULL batch or output");
+        if (launches < 1) throw Error(LBCG_EINVAL, "launches must be >= 1");
+        if (idx < 0 || idx >= (int)b->kits->size()) throw Error(LBCG_EINVAL, "variant index out of range");
+        *us = batch_time_variant(b, idx, launches);
+    });
+}
+
+lbcg_status lbcg_batch_autotune(lbcg_batch* b, int launches, int* best, double* best_us, double* all_us) {
+    return guarded([&] {
+        if (!b) throw Error(LBCG_EINVAL, "batch is NULL");
+        if (launches < 1) throw Error(LBCG_EINVAL, "launches must be >= 1");
+        int bi = 0;
+        double bt = 1e300;
+        for (int i = 0; i < (int)b->kits->size(); i++) {
+            const double t = batch_time_variant(b, i, launches);
+            if (all_us) all_us[i] = t;
+            if (t < bt) {
+                bt = t;
+                bi = i;
+            }
+        }
+        batch_select(b, bi);
+        tune_store(batch_key(b->n, b->p.data()), batch_variant_name(b, bi));
+        if (best) *best = bi;
+        if (best_us) *best_us = bt;
+    });
+}
+
+lbcg_status lbcg_tune_cache_clear(void) {
+    return guarded([&] {
+        TuneCache& c = tune_cache();
+        std::lock_guard<std::mutex> lock(c.mu);
+        c.m.clear();
+        c.loaded = true;  // the file, if any, is not read again
+    });
+}
+
 lbcg_status lbcg_batch_destroy(lbcg_batch* b) {
     if (!b) return LBCG_OK;
     for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
@@ -1427,5 +1613,10 @@ lbcg_status lbcg_batch_destroy(lbcg_batch* b) {
 }
 
 const char* lbcg_last_error(void) { return lbcg::last_error_slot().c_str(); }
+
+#ifndef LBCG_SOURCE_HASH
+#define LBCG_SOURCE_HASH "unknown"
+#endif
+const char* lbcg_source_hash(void) { return LBCG_SOURCE_HASH; }
 
 }  // extern "C"

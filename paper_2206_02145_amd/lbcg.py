@@ -55,6 +55,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
         L = ctypes.CDLL(LIB_PATH)
+        L.lbcg_source_hash.argtypes = []
+        L.lbcg_source_hash.restype = ctypes.c_char_p
+        from . import build as _build
+        built, now = L.lbcg_source_hash().decode(), _build.source_hash()
+        if built != now:
+            raise RuntimeError(f"{LIB_PATH} was built from other sources (built {built}, sources {now}); "
+                               "rebuild it: python -c 'import __graft_entry__ as g; g.build()'")
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(lbcg_params)
@@ -90,6 +97,13 @@ def lib():
         L.lbcg_batch_step_count.argtypes = [vp]
         L.lbcg_batch_step_count.restype = i64
         L.lbcg_batch_destroy.argtypes = [vp]
+        L.lbcg_batch_variant_count.argtypes = [vp]
+        L.lbcg_batch_variant_current.argtypes = [vp]
+        L.lbcg_batch_variant_name.argtypes = [vp, i32, ctypes.c_char_p, sz]
+        L.lbcg_batch_variant_select.argtypes = [vp, i32]
+        L.lbcg_batch_variant_time.argtypes = [vp, i32, i32, dp]
+        L.lbcg_batch_autotune.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int), dp, dp]
+        L.lbcg_tune_cache_clear.argtypes = []
         L.lbcg_mlp_workspace_bytes.argtypes = [i32, ctypes.POINTER(ctypes.c_int), i32]
         L.lbcg_mlp_workspace_bytes.restype = sz
         L.lbcg_mlp_create.argtypes = [i32, ctypes.POINTER(ctypes.c_int), i32, vp, sz, vp, ctypes.POINTER(vp)]
@@ -111,7 +125,10 @@ def lib():
                      "lbcg_variant_current", "lbcg_batch_create", "lbcg_batch_run", "lbcg_batch_measure",
                      "lbcg_batch_read_field", "lbcg_batch_destroy", "lbcg_mlp_create", "lbcg_mlp_set_params",
                      "lbcg_mlp_get_params", "lbcg_mlp_forward", "lbcg_mlp_grads", "lbcg_mlp_train_step",
-                     "lbcg_mlp_destroy", "lbcg_state_save", "lbcg_state_load", "lbcg_set_walls"):
+                     "lbcg_mlp_destroy", "lbcg_state_save", "lbcg_state_load", "lbcg_set_walls",
+                     "lbcg_batch_variant_count", "lbcg_batch_variant_current", "lbcg_batch_variant_name",
+                     "lbcg_batch_variant_select", "lbcg_batch_variant_time", "lbcg_batch_autotune",
+                     "lbcg_tune_cache_clear"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -355,6 +372,36 @@ class Batch:
                                    _dptr(L), 1 if use_graph else 0), "lbcg_batch_run")
         return L[:ns, :, :nd] if ns else None
 
+    def variants(self):
+        """Names of the batched step's tilings (index 0 is the default)."""
+        out = []
+        buf = ctypes.create_string_buffer(128)
+        for k in range(lib().lbcg_batch_variant_count(self.handle)):
+            check(lib().lbcg_batch_variant_name(self.handle, k, buf, 128), "lbcg_batch_variant_name")
+            out.append(buf.value.decode())
+        return out
+
+    @property
+    def variant(self) -> int:
+        return int(lib().lbcg_batch_variant_current(self.handle))
+
+    def select_variant(self, idx: int):
+        check(lib().lbcg_batch_variant_select(self.handle, int(idx)), "lbcg_batch_variant_select")
+
+    def time_variant(self, idx: int, launches: int = 20) -> float:
+        us = ctypes.c_double()
+        check(lib().lbcg_batch_variant_time(self.handle, int(idx), int(launches), ctypes.byref(us)),
+              "lbcg_batch_variant_time")
+        return us.value
+
+    def autotune(self, launches: int = 20):
+        """(best index, its microseconds per step, every tiling's microseconds); the choice is cached."""
+        best, us = ctypes.c_int(), ctypes.c_double()
+        all_us = np.zeros(max(1, lib().lbcg_batch_variant_count(self.handle)))
+        check(lib().lbcg_batch_autotune(self.handle, int(launches), ctypes.byref(best), ctypes.byref(us),
+                                        _dptr(all_us)), "lbcg_batch_autotune")
+        return best.value, us.value, all_us
+
     def measure(self, dirs):
         dirs = np.ascontiguousarray(dirs, dtype=np.float64)
         L = np.zeros((self.n, dirs.shape[0]))
@@ -388,6 +435,11 @@ class Batch:
             pass
 
 
+def tune_cache_clear():
+    """Forget the autotuner's cached choices of this process."""
+    check(lib().lbcg_tune_cache_clear(), "lbcg_tune_cache_clear")
+
+
 def _fptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
@@ -406,11 +458,7 @@ class MLP:
         nbytes = int(lib().lbcg_mlp_workspace_bytes(self.nl, self._w, self.max_batch))
         if nbytes == 0:
             raise ValueError("invalid MLP shape")
-        if ws_fill is None:
-            self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        else:
-            self.ws = torch.full((nbytes,), int(ws_fill), dtype=torch.uint8, device="cuda")
-            torch.cuda.synchronize()
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.handle = ctypes.c_void_p()
         check(lib().lbcg_mlp_create(self.nl, self._w, self.max_batch, ctypes.c_void_p(self.ws.data_ptr()), nbytes,
