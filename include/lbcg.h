@@ -186,6 +186,18 @@ lbcg_status lbcg_write_field(lbcg_handle* h, int field, const void* src, size_t 
 lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* L_out,
                          double* mass_out);
 
+/* lbcg_measure for callers that cannot allocate device memory and cannot give the solver's
+ * workspace to the diagnostics (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels and results, bit for bit, but the reduction partials, the
+ * directions and the extents live in a file-scope device array of the library (57.6 KB per device,
+ * held until the process ends) instead of in the workspace. It calls no allocation routine. The
+ * device the handle was created on must be current (EINVAL otherwise). ndirs <= 256 (EINVAL
+ * otherwise: the array holds no more). Every call on one device shares that device's array, and
+ * nothing in it needs to start at zero (each call writes every value it reads); calls that overlap
+ * on one device, on any streams, race and must be serialised by the caller. Synchronises. */
+lbcg_status lbcg_measure_noalloc(lbcg_handle* h, int ndirs, const double* dirs, double* L_out,
+                                 double* mass_out);
+
 /* A run with diagnostics, without host round trips (the measurement sequence of Section 4.1.2,
  * sizes and sums every measure_every steps): enqueue nsteps steps and, after every
  * measure_every of them, the lbcg_measure diagnostics, whose results stay on the device until the

@@ -743,6 +743,7 @@ struct lbcg_handle {
     int hist_ndirs;
     std::vector<double> hist_t;
     std::vector<double> hist_L;  // samples x ndirs
+    int device;                  // current device at creation
 };
 
 extern "C" {
@@ -787,6 +788,7 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
         hdl->red_blocks = grid_for(hdl->inst.N, RED_THREADS, RED_BLOCKS);
         hdl->nonfinite = false;
         hdl->hist_ndirs = -1;
+        HIPCHK(hipGetDevice(&hdl->device));
         SeedArgs a{p->seed_center[0], p->seed_center[1], p->seed_center[2], p->seed_radius, p->W0, p->U0,
                    p->flow ? p->u_inlet : 0.0, p->seed_tilt, p->seed_shape};
         // unused halves of the ping-pong buffers start defined (zero) so raw reads are reproducible
@@ -956,6 +958,37 @@ bool measure_into(lbcg_handle* h, int ndirs, const double* dirs, double* L_out, 
     return false;
 }
 
+// ---- the diagnostics' scratch as a file-scope device array (lbcg_measure_noalloc) ----
+// Offsets (in doubles, 256-byte aligned) of the block partials + final values, the directions and
+// the extents inside the array.
+constexpr size_t NA_PARTIALS = 0;
+constexpr size_t NA_DIRS = ((RED_BLOCKS + 1) * RED_VALUES * 8 + 255) / 256 * 256 / 8;
+constexpr size_t NA_OUT = NA_DIRS + ((size_t)MAX_DIRS * 3 * 8 + 255) / 256 * 256 / 8;
+constexpr size_t NA_DOUBLES = NA_OUT + RED_VALUES + MAX_DIRS;  // 57.6 KB
+
+}  // namespace
+
+// One copy per device, kept until the process ends. Host code never passes this name to a kernel
+// or a copy (on the host it is a stand-in, not a device address): it uses the device address
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[NA_DOUBLES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch;  // device -> address of that device's copy of `scratch`
+
+double* static_scratch(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it != g_scratch.end()) return it->second;
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Error(LBCG_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch[dev] = (double*)ptr;
+    return (double*)ptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -984,6 +1017,29 @@ lbcg_status lbcg_measure(lbcg_handle* h, int ndirs, const double* dirs, double* 
         if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
         nonfinite = measure_into(h, ndirs, dirs, L_out, mass_out, (double*)(h->ws + h->L.partials),
                                  (double*)(h->ws + h->L.dirs), (double*)(h->ws + h->L.out));
+    });
+    if (st == LBCG_OK && nonfinite) {
+        lbcg::last_error_slot() = "non-finite phi, U or rho found";
+        return LBCG_ENONFINITE;
+    }
+    return st;
+}
+
+lbcg_status lbcg_measure_noalloc(lbcg_handle* h, int ndirs, const double* dirs, double* L_out, double* mass_out) {
+    bool nonfinite = false;
+    lbcg_status st = guarded([&] {
+        if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
+        if (ndirs < 0 || ndirs > MAX_DIRS)
+            throw Error(LBCG_EINVAL, "ndirs must be in [0, " + std::to_string(MAX_DIRS) +
+                                         "] (the static scratch holds at most that many directions)");
+        if (h->red_blocks > RED_BLOCKS) throw Error(LBCG_EINVAL, "reduction larger than the static scratch");
+        int dev = -1;
+        HIPCHK(hipGetDevice(&dev));
+        if (dev != h->device)
+            throw Error(LBCG_EINVAL, "the device the handle was created on (" + std::to_string(h->device) +
+                                         ") must be current (it is " + std::to_string(dev) + ")");
+        double* base = static_scratch(dev);
+        nonfinite = measure_into(h, ndirs, dirs, L_out, mass_out, base + NA_PARTIALS, base + NA_DIRS, base + NA_OUT);
     });
     if (st == LBCG_OK && nonfinite) {
         lbcg::last_error_slot() = "non-finite phi, U or rho found";

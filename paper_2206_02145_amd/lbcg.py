@@ -74,6 +74,7 @@ def lib():
         L.lbcg_read_field.argtypes = [vp, i32, vp, sz, i32, i32]
         L.lbcg_write_field.argtypes = [vp, i32, vp, sz, i32, i32]
         L.lbcg_measure.argtypes = [vp, i32, dp, dp, dp]
+        L.lbcg_measure_noalloc.argtypes = [vp, i32, dp, dp, dp]
         L.lbcg_run.argtypes = [vp, i64, i64, i32, dp, dp, dp]
         L.lbcg_growth_rates.argtypes = [vp, dp, dp, dp]
         L.lbcg_destroy.argtypes = [vp]
@@ -120,7 +121,7 @@ def lib():
         L.lbcg_last_error.argtypes = []
         L.lbcg_last_error.restype = ctypes.c_char_p
         for name in ("lbcg_create", "lbcg_step", "lbcg_read_field", "lbcg_write_field",
-                     "lbcg_measure", "lbcg_growth_rates", "lbcg_destroy", "lbcg_variant_name",
+                     "lbcg_measure", "lbcg_measure_noalloc", "lbcg_growth_rates", "lbcg_destroy", "lbcg_variant_name",
                      "lbcg_variant_select", "lbcg_variant_time", "lbcg_autotune", "lbcg_variant_count",
                      "lbcg_variant_current", "lbcg_batch_create", "lbcg_batch_run", "lbcg_batch_measure",
                      "lbcg_batch_read_field", "lbcg_batch_destroy", "lbcg_mlp_create", "lbcg_mlp_set_params",
@@ -270,6 +271,18 @@ class Solver:
         code = lib().lbcg_measure(self.handle, nd, _dptr(dirs) if nd else None, _dptr(L), _dptr(m))
         if code != -5 or raise_nonfinite:
             check(code, "lbcg_measure")
+        mass = dict(sumU=m[0], sumPhiPrev=m[1], Vs=m[2], Mprime=m[3], umax=m[4], nonfinite=m[5])
+        return L[:nd], mass
+
+    def measure_noalloc(self, dirs=None, raise_nonfinite: bool = True):
+        """As measure, through lbcg_measure_noalloc (the library's static device scratch)."""
+        dirs = np.zeros((0, 3)) if dirs is None else np.ascontiguousarray(dirs, dtype=np.float64)
+        nd = dirs.shape[0]
+        L = np.zeros(max(nd, 1))
+        m = np.zeros(6)
+        code = lib().lbcg_measure_noalloc(self.handle, nd, _dptr(dirs) if nd else None, _dptr(L), _dptr(m))
+        if code != -5 or raise_nonfinite:
+            check(code, "lbcg_measure_noalloc")
         mass = dict(sumU=m[0], sumPhiPrev=m[1], Vs=m[2], Mprime=m[3], umax=m[4], nonfinite=m[5])
         return L[:nd], mass
 
