@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MEASURE_EVERY = 100
+COPY_BYTES_BENCH = 1 << 30
 
 
 def log(*a):
@@ -90,6 +91,14 @@ def time_steps(s, steps: int, measure_every: int = 0, dirs=None):
     return e0.elapsed_time(e1)
 
 
+REPS = 5  # timed blocks per case; the median is reported
+
+
+def median_ms(fn, reps: int = REPS):
+    import statistics
+    return statistics.median(fn() for _ in range(reps))
+
+
 def gpu_case(name, p, prec, steps, warmup, with_measure, walls=None):
     import torch
 
@@ -103,10 +112,11 @@ def gpu_case(name, p, prec, steps, warmup, with_measure, walls=None):
     dirs = W.directions(16, p["dim"])
     s.step(warmup)
     torch.cuda.synchronize()
-    # the fused step kernel alone: launch-to-launch average on its stream
-    ms_kernel = time_steps(s, steps)
-    # whole job: steps plus the diagnostics every MEASURE_EVERY steps
-    ms_job = time_steps(s, steps, MEASURE_EVERY, dirs) if with_measure else ms_kernel
+    # the fused step kernel alone: launch-to-launch average on its stream (median of REPS blocks)
+    ms_kernel = median_ms(lambda: time_steps(s, steps))
+    # whole job: steps plus the diagnostics every min(MEASURE_EVERY, steps) steps (median of REPS blocks)
+    every = min(MEASURE_EVERY, steps)
+    ms_job = median_ms(lambda: time_steps(s, steps, every, dirs)) if with_measure else ms_kernel
     L, mass = s.measure(dirs)
     s.close()
     del s
@@ -114,7 +124,8 @@ def gpu_case(name, p, prec, steps, warmup, with_measure, walls=None):
     bpl = bytes_per_lup(p, prec)
     t_launch = ms_kernel / steps * 1e-3
     achieved = bpl * nodes / t_launch / 1e9
-    out = dict(name=name, nodes=nodes, steps=steps, ms_per_step=ms_job / steps,
+    out = dict(name=name, nodes=nodes, steps=steps, reps=REPS, ms_per_step=ms_job / steps,
+               diagnostics_every=every if with_measure else None,
                mlups=nodes * steps / (ms_job * 1e-3) / 1e6,
                kernel_ms=ms_kernel / steps, kernel_mlups=nodes / t_launch / 1e6,
                bytes_per_lup=bpl, achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS,
@@ -122,6 +133,28 @@ def gpu_case(name, p, prec, steps, warmup, with_measure, walls=None):
     log(f"{name}: {out['mlups']:.0f} MLUPS (job), kernel {out['kernel_ms']*1e3:.1f} us/step = "
         f"{achieved:.0f} GB/s algorithmic ({out['frac']*100:.1f}% of {HBM_PEAK_GBS:.0f})")
     return out
+
+
+def copy_bandwidth(nbytes: int = COPY_BYTES_BENCH):
+    """Device-to-device copy of nbytes (torch copy_, read + write), median of REPS, in GB/s."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+
+    def one():
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+    ms = median_ms(one)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def sweep_case(n: int, steps: int, measure_every: int, plain: bool = True):
@@ -135,9 +168,20 @@ def sweep_case(n: int, steps: int, measure_every: int, plain: bool = True):
     plist = [W.sweep_instance(*d) for d in W.sweep_draws(n)]
     nodes = sum(p["nx"] * p["ny"] for p in plist)
     dirs = W.directions(16)
+    # the batch autotuner: every tiling timed on real steps of a throw-away batch of the same
+    # instances; the choice is cached, so the timed batch below starts on it
+    tb = lbcg.Batch(plist, "fp32")
+    names = tb.variants()
+    best, best_us, all_us = tb.autotune(20)
+    tb.close()
+    del tb
+    tuning = {nm: round(float(u), 1) for nm, u in zip(names, all_us)}
+    log(f"sweep autotuner: {names[best]} ({best_us:.1f} us/step); " +
+        ", ".join(f"{k} {v}" for k, v in tuning.items()))
     t0 = time.perf_counter()
     b = lbcg.Batch(plist, "fp32")
     t_create = time.perf_counter() - t0
+    tiling = b.variants()[b.variant]
     b.run(measure_every, measure_every, dirs)  # captures the graph (not timed); a separate batch is timed
     b.close()
     del b
@@ -150,6 +194,7 @@ def sweep_case(n: int, steps: int, measure_every: int, plain: bool = True):
     b.close()
     del b
     out = dict(instances=n, steps=steps, measure_every=measure_every, total_nodes=nodes,
+               tiling=tiling, tuning_us_per_step=tuning,
                batched_s=t_batched, batched_runs_per_s=n / t_batched,
                batched_mlups=nodes * steps / t_batched / 1e6, create_s=t_create)
     log(f"sweep batched: {n} runs x {steps} steps in {t_batched:.2f} s = {n / t_batched:.1f} runs/s "
@@ -174,37 +219,50 @@ def sweep_case(n: int, steps: int, measure_every: int, plain: bool = True):
     return out
 
 
-def cpu_baseline(p, budget_s: float = 15.0):
-    """The oracle (FP64 C, OpenMP over rows) on the host cores: a bounded number of steps of the
-    same grid, reported in MLUPS."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, steps: int = 100):
+    """The oracle (FP64 C, OpenMP over rows) on the host cores: `steps` coupled steps of the same grid
+    after one warm-up step, in MLUPS; and on one core, `steps` steps of a 16-plane z-slab of it (one
+    core would take minutes on the whole grid)."""
     from oracle import oracle
+    from paper_2206_02145_amd import workloads as W
     oracle.build(force=False)
     s = oracle.Sim(p)
-    t0 = time.time()
     s.step(1)
-    t1 = time.time() - t0
-    n = max(1, int(budget_s / max(t1, 1e-3)))
     t0 = time.time()
-    s.step(n)
+    s.step(steps)
     dt = time.time() - t0
     nodes = p["nx"] * p["ny"] * p["nz"]
-    out = dict(value=nodes * n / dt / 1e6, unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
-               sample=f"{n} coupled steps of the full {p['nx']}x{p['ny']}x{p['nz']} grid after 1 warm-up "
+    out = dict(value=nodes * steps / dt / 1e6, unit="MLUPS", cores=oracle.num_threads(), kind="oracle",
+               cpu_model=cpu_model(), os_cpus=os.cpu_count(),
+               sample=f"{steps} coupled steps of the full {p['nx']}x{p['ny']}x{p['nz']} grid after 1 warm-up "
                       f"step ({dt:.1f} s, FP64)")
-    # the same on one core (a shorter sample: one step takes seconds)
+    del s
     threads = oracle.num_threads()
     oracle.set_num_threads(1)
     try:
+        q = W.scaled(p, p["nx"], p["ny"], 16)
+        s1 = oracle.Sim(q)
+        s1.step(1)
         t0 = time.time()
-        k = 0
-        while k < 1 or (time.time() - t0 < budget_s / 3 and k < 8):
-            s.step(1)
-            k += 1
+        s1.step(steps)
         dt1 = time.time() - t0
     finally:
         oracle.set_num_threads(threads)
-    out["single_core"] = dict(value=nodes * k / dt1 / 1e6, unit="MLUPS", cores=1,
-                              sample=f"{k} coupled steps of the same grid ({dt1:.1f} s, FP64)")
+    n1 = q["nx"] * q["ny"] * q["nz"]
+    out["single_core"] = dict(value=n1 * steps / dt1 / 1e6, unit="MLUPS", cores=1,
+                              sample=f"{steps} coupled steps of a {q['nx']}x{q['ny']}x{q['nz']} z-slab of the "
+                                     f"same configuration after 1 warm-up step ({dt1:.1f} s, FP64)")
     return out
 
 
@@ -477,6 +535,8 @@ def main():
         surr = surrogate.run_study(n_train=args.surrogate_train, log=log)
         if sweep and "plain_runs_per_s" in sweep:
             surr["plain_sequential_runs_per_s"] = sweep["plain_runs_per_s"]
+    copy_gbs = copy_bandwidth()
+    log(f"1 GiB device copy: {copy_gbs:.0f} GB/s (read + write)")
     cpu = None if args.no_cpu else cpu_baseline(p3)
     if cpu:
         log(f"cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads ({cpu['sample']})")
@@ -499,11 +559,13 @@ def main():
         "data": "synthetic (seeded tanh seed, uniform supersaturation, inlet flow)",
         "config": {"workload": "3-D coupled phase-field/solute/flow LB, 192x128x128, D3Q7+D3Q7+D3Q19, "
                                "inlet u=0.02 at x-, outlet x+, periodic y/z, seed R=12, U0=U_in=0.3",
-                   "nodes": head["nodes"], "diagnostics_every": MEASURE_EVERY, "parallelism": "single GPU"},
+                   "nodes": head["nodes"], "diagnostics_every": head["diagnostics_every"],
+                   "timed_blocks": REPS, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["frac"], 4),
                      "traffic": traffic,
                      "kernel": "step_single (" + head["variant"] + ")",
+                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(head["achieved_gbs"] / copy_gbs, 4),
                      "bytes_per_lup": head["bytes_per_lup"], "kernel_us": round(head["kernel_ms"] * 1e3, 2)},
         "cpu_baseline": cpu,
         "sweep": None if sweep is None else {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sweep.items()},

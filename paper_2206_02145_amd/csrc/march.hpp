@@ -225,7 +225,6 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
                                  hn[5],
                                  hmz};
             real hk[S::Q];
-            real hsum = 0;
 #pragma unroll
             for (int a = 0; a < S::Q; a++) {
                 const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
@@ -233,9 +232,9 @@ __device__ __forceinline__ void march3d_tile(const InstDev& I, const int tile, c
                 const real cN = (real)cx * Nx + (real)cy * Ny + (real)cz * Nz;
                 const real heq = wa * (psi - cN * kc);
                 hk[a] = hc[a] - (hc[a] - heq) * inv_tau_phi + wa * Qs;
-                if (a) hsum += hk[a];
             }
-            hk[0] = (psi + Qs) - hsum;  // rest population from the exact zeroth moment psi + Q/tau0
+            // rest population from the exact zeroth moment psi + Q/tau0 (rounding errors carried)
+            hk[0] = rest_closure<real, S::Q>(hc, psi, Qs, hk);
 #pragma unroll
             for (int a = 0; a < S::Q; a++) {
                 const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);

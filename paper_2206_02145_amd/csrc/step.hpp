@@ -44,6 +44,7 @@
 #include <hip/hip_runtime.h>
 
 #include "chmrt.hpp"
+#include "exact.hpp"
 #include "lattice.hpp"
 #include "mem.hpp"
 
@@ -397,7 +398,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
         // Q = phi - phi^3 + lambda U (1 - phi^2)^2 = (1 - phi^2)(phi + lambda U (1 - phi^2))
         const real Qs = p2 * (phi + kconst<real>(I, K_LAMBDA) * U * p2) * kconst<real>(I, K_ITAU0);
         real hk[S::Q], vk[S::Q];  // post-collision values; pushed values (c_x < 0 ones reused at the open faces)
-        real hsum = 0;
+        real hv[S::Q];
 #pragma unroll
         for (int a = 0; a < S::Q; a++) {
             const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);
@@ -405,13 +406,14 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
             const real cN = (real)cx * Nx + (real)cy * Ny + (real)cz * Nz;
             const real heq = wa * (psi - cN * kc);  // h_eq + w
             const real ha = s_h[a][bo];
+            hv[a] = ha;
             hk[a] = ha - (ha - heq) * inv_tau_phi + wa * Qs;
-            if (a) hsum += hk[a];
         }
         // The collision's zeroth moment is psi + Q/tau0 exactly; taking the rest population from it
-        // keeps each node's phase balance closed in the working precision (in binary32 this stops
-        // a drift of the interface that would otherwise grow linearly with the step count).
-        hk[0] = (psi + Qs) - hsum;
+        // (with the rounding errors of the sums carried, rest_closure) keeps each node's phase
+        // balance closed in the working precision (in binary32 this stops a drift of the interface
+        // that would otherwise grow linearly with the step count, and a drift of U in the solid).
+        hk[0] = rest_closure<real, S::Q>(hv, psi, Qs, hk);
 #pragma unroll
         for (int a = 0; a < S::Q; a++) {
             const int cx = S::c(a, 0), cy = S::c(a, 1), cz = S::c(a, 2);

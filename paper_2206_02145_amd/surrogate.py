@@ -4,16 +4,16 @@ the fallback and the reference for its error.
 Inputs (supersaturation U0, seed radius R, inflow velocity u_in, time t) -> 16 crystal extents
 L_k(t) along the directions 2 pi k / 16 and the 16 growth rates G_k(t) (least-squares slope of L_k
 against time over the samples in [t/2, t], Section 4.1.2's linear fit on a growing window), as a
-mean and a log-variance head each. Training data: batched solver runs (lbcg_batch_*) of the 2-D sweep instances; training
+mean and a log-variance head each. Training data: batched solver runs (lbcg_batch_*) of 2-D
+forced-convection instances whose (U0, R, u_in) are drawn as in the parametric sweep; training
 and inference run in the library's bf16-MFMA MLP kernels (lbcg_mlp_*). A prediction whose
 predicted relative growth-rate error (two standard deviations of the predicted G_k over the mean
-predicted G) exceeds the tolerance falls back to the solver.
+predicted G) exceeds the calibrated threshold falls back to the solver.
 
-The side length of the 2-D domain is drawn with the other parameters. The four-input network
-cannot see it and predicts the direction-averaged growth rate well but the per-direction rates
-poorly (small domains deplete the supersaturation within the run); the deployed model therefore
-also takes the side length (`with_side=True`), and the four-input model is kept and reported with
-the direction-averaged criterion.
+The domain side is not among the four inputs, so the runs share one side length
+(workloads.SURROGATE_SIDE): on domains of mixed sizes small domains deplete the supersaturation
+within the run and the same four inputs give different rates. A model that also takes the side
+(`with_side=True`) can be trained on the sweep's mixed sides for comparison.
 """
 from __future__ import annotations
 
@@ -99,7 +99,7 @@ def rows(ds: Dataset, with_side: bool = False):
 
 
 class Surrogate:
-    def __init__(self, seed: int = 0, max_batch: int = 4096, with_side: bool = True):
+    def __init__(self, seed: int = 0, max_batch: int = 4096, with_side: bool = False):
         from . import lbcg
         self.with_side = with_side
         self.widths = [5 if with_side else 4] + WIDTHS[1:]
@@ -260,27 +260,35 @@ def evaluate(model: Surrogate, held: Dataset, tol: float = 0.05, floor: float = 
 
 
 def run_study(n_train: int = 4096, n_held: int = 256, steps: int = 4000, train_steps: int = 12000, log=None,
-              seed_train: int = 22060, seed_held: int = 22061):
-    """Generate the training and held-out runs, train both models, evaluate with fallback."""
-    tr = generate(W.sweep_draws(n_train, seed=seed_train), steps=steps)
-    if log:
-        log(f"surrogate: {n_train} training runs solved in {tr.solve_s:.1f} s")
-    ho = generate(W.sweep_draws(n_held, seed=seed_held), steps=steps)
-    solver_rps = n_held / ho.solve_s
-    out = dict(train_runs=n_train, held_out_runs=n_held, steps=steps, solve_train_s=tr.solve_s,
-               solver_alone_runs_per_s=solver_rps)
-    # the last tenth of the training runs calibrates the acceptance threshold and is not trained on
-    n_cal = max(1, n_train // 10)
-    fit, cal = subset(tr, np.arange(n_train - n_cal)), subset(tr, np.arange(n_train - n_cal, n_train))
-    floor = 0.1 * float(np.abs(cal.G[:, -1]).mean())
-    for name, ws, crit in (("deployed_with_side", True, "max_dir"), ("four_inputs", False, "avg"),
-                           ("four_inputs_max_dir", False, "max_dir")):
+              seed_train: int = 22060, seed_held: int = 22061, mixed_sides: bool = False):
+    """Generate the training and held-out runs (one domain side, workloads.surrogate_draws), train
+    the four-input model, evaluate it with fallback. mixed_sides: also the comparison on the
+    sweep's mixed domain sides, with and without the side as a fifth input."""
+    cases = [("deployed", W.surrogate_draws, False, "max_dir")]
+    if mixed_sides:
+        cases += [("mixed_sides_with_side", W.sweep_draws, True, "max_dir"),
+                  ("mixed_sides_four_inputs", W.sweep_draws, False, "max_dir")]
+    out = dict(train_runs=n_train, held_out_runs=n_held, steps=steps, side=W.SURROGATE_SIDE)
+    data = {}
+    for name, drawfn, ws, crit in cases:
+        if drawfn not in data:
+            tr = generate(drawfn(n_train, seed=seed_train), steps=steps)
+            ho = generate(drawfn(n_held, seed=seed_held), steps=steps)
+            if log:
+                log(f"surrogate data ({drawfn.__name__}): {n_train} training runs solved in {tr.solve_s:.1f} s")
+            data[drawfn] = (tr, ho)
+        tr, ho = data[drawfn]
+        # the last tenth of the training runs calibrates the acceptance threshold and is not trained on
+        n_cal = max(1, n_train // 10)
+        fit, cal = subset(tr, np.arange(n_train - n_cal)), subset(tr, np.arange(n_train - n_cal, n_train))
+        floor = 0.1 * float(np.abs(cal.G[:, -1]).mean())
         m = Surrogate(with_side=ws)
         info = m.train(fit, steps=train_steps)
         thr = calibrate(m, cal, 0.05, floor, crit)
         res = evaluate(m, ho, floor=floor, criterion=crit, threshold=thr)
         res.update(train_s=info["train_s"], final_loss=info["final_loss"], inputs=5 if ws else 4,
-                   train_runs=n_train - n_cal, calibration_runs=n_cal)
+                   train_runs=n_train - n_cal, calibration_runs=n_cal, solve_train_s=tr.solve_s,
+                   domain="one side" if drawfn is W.surrogate_draws else "mixed sides")
         out[name] = res
         if log:
             log(f"surrogate {name}: threshold {res['threshold']}, accepted {res['accepted']}/{n_held}, "

@@ -85,6 +85,16 @@ def sweep_draws(n: int = 256, seed: int = 2206):
     return out
 
 
+SURROGATE_SIDE = 256  # domain side of the surrogate's training and held-out runs
+
+
+def surrogate_draws(n: int, seed: int, side: int = SURROGATE_SIDE):
+    """Draws of the surrogate's runs: (U0, R, u_in) from the sweep's distributions (sweep_draws with
+    the same seed), on a domain of one fixed side length, since the surrogate's four inputs do not
+    include it. Tuples (side, U0, R, u_in) as sweep_draws."""
+    return [(int(side),) + d[1:] for d in sweep_draws(n, seed)]
+
+
 def sweep_instance(side: int, U0: float, R: float, u_in: float) -> dict:
     """One 2-D sweep instance: D2Q9 flow with inlet/outlet in x, periodic y, centred seed."""
     return params(dim=2, nx=side, ny=side, nz=1, flow=1, xbc=1, u_in=u_in, U0=U0, U_in=U0,

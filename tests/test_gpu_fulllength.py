@@ -23,7 +23,7 @@ from paper_2206_02145_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-CASES = {"c2": W.config2, "c3": W.config3}
+CASES = {"c2": W.config2, "c3": W.config3, "c3r": W.config3_reduced}
 
 
 @pytest.fixture(scope="module")
@@ -132,3 +132,43 @@ def test_full_length_flow_fp64(lb):
     for k, v in errs.items():  # measured 1.5e-3 (phi): rounding-order differences amplified ~20x per 2000 steps
         assert v <= 1e-2, (k, v)
     s.close()
+
+
+# Binary32 against the oracle on the 96x64x64 flow grid at eps = 0.02 (interface stiffness positive:
+# no amplification of rounding), per snapshot. phi, rho and u stay within 1e-4 through the
+# 20000 steps. U meets 1e-4 through 8000 steps; after that its error grows about linearly in the
+# crystal, where q = 1 - phi = 0 makes tau_U exactly 1/2 and the solute's non-equilibrium mode is
+# undamped, so the last-place noise of phi = sum h that reaches it through the source -dphi/dt
+# accumulates (measured against the oracle: 1.7e-5, 4.9e-5, 1.2e-4, 2.0e-4 and 2.5e-4 at
+# 4000 .. 20000 steps; 2.3e-4 at 8000 and 9.3e-4 at 20000 without the compensated closure of the
+# phase-field collision).
+C3R_U_BAR = {4000: 1e-4, 8000: 1e-4, 12000: 1.6e-4, 16000: 2.6e-4, 20000: 3.2e-4}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_reduced_flow_grid_every_4000_steps(lb, prec):
+    snaps = {}
+    for step in (4000, 8000, 12000, 16000, None):
+        z, meta, p = load("c3r", step)
+        snaps[meta["steps"]] = z
+    p = W.config3_reduced()
+    s = lb.Solver(p, prec)
+    done = 0
+    for step in sorted(snaps):
+        s.step(step - done)
+        done = step
+        z = snaps[step]
+        errs = errors(s, z, p)
+        dL, dVs, dM = aggregates(s, z)
+        print(f"[fulllength] c3r {prec} @{step}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
+              f"; max |dL| {dL:.2e} cells; Vs {dVs:.2e}; M' {dM:.2e}", flush=True)
+        if prec == "fp64":
+            for k, v in errs.items():
+                assert v <= 1e-10, (step, k, v)
+            assert dL <= 1e-8 and dVs <= 1e-11 and dM <= 1e-11
+        else:
+            for k, v in errs.items():
+                assert v <= (C3R_U_BAR[step] if k == "U" else 1e-4), (step, k, v)
+            assert dL <= 0.01 and dVs <= 1e-4
+    s.close()
+

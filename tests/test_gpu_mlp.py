@@ -51,6 +51,7 @@ def test_forward_matches_reference(lb, B):
 
 
 def test_gradients_match_reference(lb):
+    """Every gradient element against the reference: per tensor, max |g - g_ref| / max |g_ref|."""
     import torch
     flat = init(WIDTHS, seed=2)
     net = lb.MLP(WIDTHS, 512)
@@ -64,10 +65,46 @@ def test_gradients_match_reference(lb):
     assert abs(loss - lr_) < 1e-5 * abs(lr_)
     gl = M.unpack(WIDTHS, g.astype(np.float64))
     for l, ((gW, gb), (rW, rb)) in enumerate(zip(gl, grads)):
-        eW = np.linalg.norm(gW - rW) / np.linalg.norm(rW)
-        eb = np.linalg.norm(gb - rb) / np.linalg.norm(rb)
-        print(f"[mlp] layer {l} grad rel err W {eW:.2e} b {eb:.2e}")
-        assert eW < 1e-2 and eb < 1e-2, l
+        eW = np.abs(gW - rW).max() / np.abs(rW).max()
+        eb = np.abs(gb - rb).max() / np.abs(rb).max()
+        print(f"[mlp] layer {l} grad elementwise max err / max |ref|: W {eW:.2e} b {eb:.2e}")
+        assert eW < GRAD_TOL and eb < GRAD_TOL, l
+    net.close()
+
+
+# The reference rounds to bf16 at the same points; an activation whose fp32 accumulation lands on
+# the other side of a bf16 rounding boundary than the fp64 one changes by 2^-8 relative, and the
+# gradient elements that depend on it follow.
+GRAD_TOL = 2e-2
+
+
+def test_adam_update_matches_reference_elementwise(lb):
+    """Adam in the library against the reference Adam fed the same gradients (those the library
+    computes for the same batch): every parameter after 10 steps, max |w - w_ref| / max |w_ref - w0|
+    per tensor."""
+    import torch
+    widths = [4, 64, 64, 8]
+    flat = init(widths, seed=8)
+    net = lb.MLP(widths, 256)
+    net.set_params(flat)
+    x, t = data(512, seed=9)
+    t = t[:, :4].copy()
+    X, T = torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda")
+    opt = M.Adam(flat.size, lr=2e-3)
+    w = flat.astype(np.float64)
+    rng = np.random.default_rng(10)
+    for k in range(10):
+        idx = torch.tensor(rng.permutation(512)[:128].astype(np.int32), device="cuda")
+        g, _ = net.grads(X, T, idx)          # the gradients train_step computes for this batch
+        net.train_step(X, T, idx, lr=2e-3)
+        w = opt.step(w, g.astype(np.float64))
+        wg = net.get_params().astype(np.float64)
+        for l, ((a, ab), (r, rb), (o, ob)) in enumerate(zip(M.unpack(widths, wg), M.unpack(widths, w),
+                                                            M.unpack(widths, flat.astype(np.float64)))):
+            for name, u, v, v0 in (("W", a, r, o), ("b", ab, rb, ob)):
+                e = np.abs(u - v).max() / np.abs(v - v0).max()
+                assert e < 1e-4, (k, l, name, e)
+    print(f"[mlp] Adam, 10 steps, elementwise: max |w - w_ref| / max |w_ref - w0| < 1e-4 in every tensor")
     net.close()
 
 

@@ -12,8 +12,8 @@ def study():
         pytest.skip("no HIP device")
     from paper_2206_02145_amd import surrogate as S
     from paper_2206_02145_amd import workloads as W
-    tr = S.generate(W.sweep_draws(768, seed=5), steps=2000)
-    ho = S.generate(W.sweep_draws(96, seed=6), steps=2000)
+    tr = S.generate(W.surrogate_draws(768, seed=5, side=128), steps=2000)
+    ho = S.generate(W.surrogate_draws(96, seed=6, side=128), steps=2000)
     return S, tr, ho
 
 
@@ -29,10 +29,12 @@ def test_dataset_records_growth(study):
 
 
 def test_surrogate_gains_over_the_solver_alone(study):
-    """Accepted predictions are within the tolerance and the surrogate with fallback answers more
-    runs per second than the batched solver alone."""
+    """The four-input model (supersaturation, seed radius, inflow velocity, time) on runs of one domain
+    side: every accepted prediction is within the 5 % growth-rate tolerance, and the surrogate with
+    fallback answers more runs per second than the batched solver alone."""
     S, tr, ho = study
-    m = S.Surrogate(with_side=True)
+    m = S.Surrogate(with_side=False)
+    assert m.widths[0] == 4
     n = len(tr.draws)
     fit, cal = S.subset(tr, np.arange(n - 96)), S.subset(tr, np.arange(n - 96, n))
     info = m.train(fit, steps=2500)
@@ -41,7 +43,8 @@ def test_surrogate_gains_over_the_solver_alone(study):
     res = S.evaluate(m, ho, floor=floor, threshold=thr)
     print("[surrogate]", info, res, flush=True)
     assert 0 < thr <= 0.05
-    assert res["accepted"] >= 0.2 * res["held_out"]
-    assert res["accepted_within_tol"] >= 0.9
-    assert res["runs_per_s"] > res["solver_alone_runs_per_s"]
+    assert res["accepted"] >= 0.5 * res["held_out"]
+    assert res["accepted_within_tol"] == 1.0
+    assert res["delivered_err_max"] <= 0.05
+    assert res["runs_per_s"] > 1.5 * res["solver_alone_runs_per_s"]
     m.net.close()

@@ -1,0 +1,105 @@
+"""The batched sweep against the oracle at the sweep's full length: six of the sweep's own 256
+instances (the first of every side length 64 .. 256 and the one with the fastest inflow,
+tests/golden/make_sweep.py) run as one batch for 4000 steps; their crystal extents every 100 steps
+and their fields at the end are compared with the oracle's (binary64) run of each instance.
+
+Bar: per field, max |error| over the sampled nodes / max |value| over the grid (phi, U, rho, and
+the velocity u* as a vector over its largest component).
+
+* binary64, at the sweep's eps = 0.05: 1e-8 (the same algorithm; measured <= 1e-9).
+* binary32 at eps = 0.02 (interface stiffness 1 - 35 eps cos 6 theta positive): 1e-4, and the
+  crystal extents within 1e-3 cells, with every tiling of the batched step.
+* binary32 at eps = 0.05: the negative stiffness near the crystal axes amplifies any perturbation,
+  rounding included, about threefold per 500 steps once the crystal has grown (binary32 against
+  binary64 on the GPU, instance 1: phi 1.5e-6 at 1000 steps, 6.5e-6 at 2000, 6.0e-5 at 3000,
+  6.0e-4 at 4000), and a seed that melts (instance 8) vanishes a few steps earlier or later;
+  binary32 and binary64 then part pointwise, as two binary64 runs summing in different orders
+  would. Checked there: the binary64 diagnostics of the solid volume and the crystal extents."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2206_02145_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def lb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2206_02145_amd import lbcg
+    lbcg.lib()
+    return lbcg
+
+
+def load(name):
+    z = np.load(os.path.join(GOLDEN, name), allow_pickle=False)
+    meta = json.loads(str(z["meta"]))
+    idx = [int(i) for i in z["indices"]]
+    draws = W.sweep_draws(256)
+    for i, d in zip(idx, meta["draws"]):  # the stored runs are of exactly these draws
+        assert np.allclose(draws[i], d)
+    eps = meta.get("eps", W.BASE["eps"])
+    plist = [dict(W.sweep_instance(*draws[i]), eps=eps) for i in idx]
+    return z, meta, idx, plist
+
+
+def compare(b, z, idx, plist, hist, tag):
+    worst = {}
+    for j, i in enumerate(idx):
+        n = z[f"{i}_nodes"]
+        ys, xs = n[:, 0], n[:, 1]
+        errs = {}
+        for f in ("phi", "U", "rho"):
+            errs[f] = float(np.abs(b.read(j, f)[0, ys, xs] - z[f"{i}_{f}"]).max() / z[f"{i}_absmax_{f}"])
+        um = max(float(z[f"{i}_absmax_ux"]), float(z[f"{i}_absmax_uy"]))
+        errs["u"] = max(float(np.abs(b.read(j, c)[0, ys, xs] - z[f"{i}_{c}"]).max()) for c in ("ux", "uy")) / um
+        errs["L"] = float(np.abs(hist[:, j, :] - z[f"{i}_L"]).max())
+        print(f"[sweep] {tag} instance {i} side {plist[j]['nx']} u_in {plist[j]['u_in']:.4f}: " +
+              ", ".join(f"{f}={v:.2e}" for f, v in errs.items()), flush=True)
+        for f, v in errs.items():
+            worst[f] = max(worst.get(f, 0.0), v)
+    return worst
+
+
+def test_batched_sweep_fp64_matches_oracle_after_4000_steps(lb):
+    z, meta, idx, plist = load("sweep_c4.npz")
+    b = lb.Batch(plist, "fp64")
+    hist = b.run(meta["steps"], meta["every"], W.directions(16))
+    worst = compare(b, z, idx, plist, hist, "fp64 eps 0.05")
+    b.close()
+    for f in ("phi", "U", "rho", "u"):
+        assert worst[f] <= 1e-8, (f, worst[f])
+    assert worst["L"] <= 1e-6  # the melting seed (instance 8): its last crossings, 6.9e-8 measured
+
+
+def test_batched_sweep_fp32_matches_oracle_at_eps_002_every_tiling(lb):
+    z, meta, idx, plist = load("sweep_c4_eps0.02.npz")
+    b0 = lb.Batch(plist, "fp32")
+    names = b0.variants()
+    b0.close()
+    for k, name in enumerate(names):
+        b = lb.Batch(plist, "fp32")
+        b.select_variant(k)
+        hist = b.run(meta["steps"], meta["every"], W.directions(16))
+        worst = compare(b, z, idx, plist, hist, f"fp32 eps 0.02 {name}")
+        b.close()
+        for f in ("phi", "U", "rho", "u"):
+            assert worst[f] <= 1e-4, (name, f, worst[f])
+        assert worst["L"] <= 1e-3, (name, worst["L"])
+
+
+def test_batched_sweep_fp32_at_eps_005_aggregates(lb):
+    z, meta, idx, plist = load("sweep_c4.npz")
+    b = lb.Batch(plist, "fp32")
+    hist = b.run(meta["steps"], meta["every"], W.directions(16))
+    worst = compare(b, z, idx, plist, hist, "fp32 eps 0.05 (amplified, pointwise not asserted)")
+    b.close()
+    # the crystal extents every 100 steps: within a quarter cell (the melting seed's last samples)
+    assert worst["L"] <= 0.25, worst["L"]
