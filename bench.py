@@ -533,8 +533,6 @@ def main():
     if not args.no_surrogate:
         from paper_2206_02145_amd import surrogate
         surr = surrogate.run_study(n_train=args.surrogate_train, log=log)
-        if sweep and "plain_runs_per_s" in sweep:
-            surr["plain_sequential_runs_per_s"] = sweep["plain_runs_per_s"]
     copy_gbs = copy_bandwidth()
     log(f"1 GiB device copy: {copy_gbs:.0f} GB/s (read + write)")
     cpu = None if args.no_cpu else cpu_baseline(p3)

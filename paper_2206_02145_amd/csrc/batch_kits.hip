@@ -12,10 +12,11 @@
 namespace lbcg {
 namespace {
 
-template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, bool CHM = false>
+template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, bool CHM = false,
+          int LAUX = 0, int HAUX = -1>
 struct BatchImpl {
     static void step(const InstDev* d, int n, int tiles, int par, hipStream_t s) {
-        hipLaunchKernelGGL((step_batch<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, 0, CHM>), dim3(tiles),
+        hipLaunchKernelGGL((step_batch<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, CHM, HAUX>), dim3(tiles),
                            dim3(TX * TY * TZ), 0, s, d, n, par);
     }
     static void ray(const InstDev* d, int n, int par, const double* dirs, int ndirs, const double* centers,
@@ -24,8 +25,9 @@ struct BatchImpl {
                            centers, out);
     }
     static BatchKit kit() {
-        Tiling t{false, TX, TY, TZ, PF, AUX, 0, 0};
+        Tiling t{false, TX, TY, TZ, PF, AUX, LAUX, 0};
         t.chm = CHM;
+        t.haux = HAUX;
         return BatchKit{t, step, ray};
     }
 };
@@ -45,6 +47,9 @@ std::vector<BatchKit> kits_of() {
             v.push_back(BatchImpl<2, FLOW, real, fst, 64, 2, 1, true, 2, CHM>::kit());
             v.push_back(BatchImpl<2, FLOW, real, fst, 64, 8, 1, false, 2, CHM>::kit());
             v.push_back(BatchImpl<2, FLOW, real, fst, 128, 2, 1, false, 2, CHM>::kit());
+            // streaming loads and stores of g, f and phi_prev, h kept in the caches
+            v.push_back(BatchImpl<2, FLOW, real, fst, 64, 4, 1, false, 2, CHM, 2, 0>::kit());
+            v.push_back(BatchImpl<2, FLOW, real, fst, 64, 8, 1, false, 2, CHM, 2, 0>::kit());
         } else {
             v.push_back(BatchImpl<2, FLOW, real, fst, 64, 8, 1, false, 2, CHM>::kit());
         }
@@ -57,6 +62,7 @@ std::vector<BatchKit> kits_of() {
             v.push_back(BatchImpl<3, FLOW, real, fst, 64, 2, 4, false, 0, CHM>::kit());
             v.push_back(BatchImpl<3, FLOW, real, fst, 64, 4, 2, true, 0, CHM>::kit());
             v.push_back(BatchImpl<3, FLOW, real, fst, 64, 2, 2, true, 0, CHM>::kit());
+            v.push_back(BatchImpl<3, FLOW, real, fst, 64, 2, 4, false, 2, CHM, 2, 0>::kit());
         } else {
             v.push_back(BatchImpl<3, FLOW, real, fst, 64, 2, 2, true, 0, CHM>::kit());
         }

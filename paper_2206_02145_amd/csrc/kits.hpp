@@ -21,6 +21,7 @@ struct Tiling {
     int zband = 0;  // z tile-layers per band of the block tile order (0: plain x, y, z order)
     bool walls = false;  // the kernel honours the solid-wall mask
     bool chm = false;    // central-Hermite MRT flow collision
+    int haux = -1;       // cache policy of the h stores (-1: aux)
 };
 
 // One compiled tiling of the batched step (every instance's tiles in one launch) and its

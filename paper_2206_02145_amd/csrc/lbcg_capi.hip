@@ -281,18 +281,19 @@ struct CommonOps {
 };
 
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
-          int LAUX = 0, bool WALLS = false, bool CHM = false>
+          int LAUX = 0, bool WALLS = false, bool CHM = false, int HAUX = -1>
 struct BlockOps : CommonOps<DIM, FLOW, real, fst> {
     using C = CommonOps<DIM, FLOW, real, fst>;
     static void step(const InstDev& I, int par, hipStream_t s) {
         const int nblocks = I.tiles_x * I.tiles_y * I.tiles_z;
-        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM>), dim3(nblocks),
-                           dim3(TX * TY * TZ), 0, s, I, par);
+        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM, HAUX>),
+                           dim3(nblocks), dim3(TX * TY * TZ), 0, s, I, par);
     }
     static Ops ops() {
         Tiling t{false, TX, TY, TZ, PF, AUX, LAUX, 0};
         t.walls = WALLS;
         t.chm = CHM;
+        t.haux = HAUX;
         return Ops{t, step, C::init, C::field, C::reduce, C::ray};
     }
 };
@@ -339,14 +340,18 @@ void block_variants(std::vector<Variant>& v, bool large) {
         static const Ops c = BlockOps<2, FLOW, real, fst, 64, 2, 1, true, 2>::ops();
         static const Ops d = BlockOps<2, FLOW, real, fst, 64, 8, 1, false, 2>::ops();
         static const Ops e = BlockOps<2, FLOW, real, fst, 128, 2, 1, false, 2>::ops();
-        // the batched launch uses the first of these (64 x 4, streaming stores in binary32)
-        if (large || sizeof(real) == 8) for (const Ops* o : {&a, &a0, &b, &c, &d, &e}) add(*o);
-        else for (const Ops* o : {&a0, &a, &b, &c, &d, &e}) add(*o);
+        // streaming loads and stores of g, f and phi_prev, h kept in the caches (see step_tile)
+        static const Ops k = BlockOps<2, FLOW, real, fst, 64, 4, 1, false, 2, 2, false, false, 0>::ops();
+        static const Ops k8 = BlockOps<2, FLOW, real, fst, 64, 8, 1, false, 2, 2, false, false, 0>::ops();
+        if (large) for (const Ops* o : {&k, &a, &a0, &b, &c, &d, &e, &k8}) add(*o);
+        else if (sizeof(real) == 8) for (const Ops* o : {&a, &a0, &b, &c, &d, &e, &k, &k8}) add(*o);
+        else for (const Ops* o : {&a0, &a, &b, &c, &d, &e, &k, &k8}) add(*o);
     } else if constexpr (sizeof(real) == 8) {
         static const Ops a = BlockOps<3, FLOW, real, fst, 16, 4, 4>::ops();
         static const Ops b = BlockOps<3, FLOW, real, fst, 32, 2, 4, true>::ops();
-        add(a);
-        add(b);
+        static const Ops k = BlockOps<3, FLOW, real, fst, 16, 4, 4, false, 2, 2, false, false, 0>::ops();
+        if (large) for (const Ops* o : {&k, &a, &b}) add(*o);
+        else for (const Ops* o : {&a, &b, &k}) add(*o);
     } else {
         static const Ops a0 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 0>::ops();
         static const Ops a1 = BlockOps<3, FLOW, real, fst, 64, 2, 4, true, 0>::ops();
@@ -360,16 +365,19 @@ void block_variants(std::vector<Variant>& v, bool large) {
         static const Ops c1 = BlockOps<3, FLOW, real, fst, 32, 8, 2, true>::ops();
         static const Ops c2 = BlockOps<3, FLOW, real, fst, 32, 4, 4, true>::ops();
         static const Ops d0 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2>::ops();
+        // streaming loads and stores of g, f and phi_prev, h kept in the caches (see step_tile)
+        static const Ops k0 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, false, false, 0>::ops();
         auto band = [&](const Ops& o, int zband) {  // the same kernel with a banded tile order
             Tiling t = o.tiling;
             t.zband = zband;
             v.push_back({&o, t});
         };
-        // first = default: 64 x 2 x 4 (one wavefront per x-row); streaming stores when the two
-        // population copies exceed the last-level cache (the fastest measured on the
-        // 192 x 128 x 128 flow grid, also with binary16 flow storage)
-        if (large) for (const Ops* o : {&a2, &a3, &a0, &a1, &d0}) add(*o);
-        else for (const Ops* o : {&a0, &a1, &a2, &a3, &d0}) add(*o);
+        // first = default: 64 x 2 x 4 (one wavefront per x-row); when the two population copies
+        // exceed the last-level cache, streaming loads and stores of g, f and phi_prev with h kept in
+        // the caches (the fastest measured on the 192 x 128 x 128 flow grid, also with binary16
+        // flow storage); below that size, the default policy everywhere
+        if (large) for (const Ops* o : {&k0, &a2, &a3, &a0, &a1, &d0}) add(*o);
+        else for (const Ops* o : {&a0, &a1, &a2, &a3, &d0, &k0}) add(*o);
         for (int zb : {2, 4, 8}) band(large ? a2 : a0, zb);
         band(large ? a3 : a1, 4);
         for (const Ops* o : {&b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
@@ -390,13 +398,9 @@ std::vector<Variant> wall_variants(bool large) {
     } else {
         static const Ops a = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 0, 0, true>::ops();
         static const Ops b = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 0, true>::ops();
-        if (large) {
-            add(b);
-            add(a);
-        } else {
-            add(a);
-            add(b);
-        }
+        static const Ops k = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, true, false, 0>::ops();
+        if (large) for (const Ops* o : {&k, &b, &a}) add(*o);
+        else for (const Ops* o : {&a, &b, &k}) add(*o);
     }
     return v;
 }
@@ -410,14 +414,11 @@ std::vector<Variant> chm_variants(bool large, bool walls) {
         static const Ops a = BlockOps<2, true, real, fst, 64, 4, 1, false, 0, 0, false, true>::ops();
         static const Ops b = BlockOps<2, true, real, fst, 64, 4, 1, false, 2, 0, false, true>::ops();
         static const Ops w = BlockOps<2, true, real, fst, 64, 4, 1, false, 0, 0, true, true>::ops();
+        static const Ops k = BlockOps<2, true, real, fst, 64, 4, 1, false, 2, 2, false, true, 0>::ops();
         if (walls) add(w);
-        else if (large || sizeof(real) == 8) {
-            add(b);
-            add(a);
-        } else {
-            add(a);
-            add(b);
-        }
+        else if (large) for (const Ops* o : {&k, &b, &a}) add(*o);
+        else if (sizeof(real) == 8) for (const Ops* o : {&b, &a, &k}) add(*o);
+        else for (const Ops* o : {&a, &b, &k}) add(*o);
     } else if constexpr (sizeof(real) == 8) {
         static const Ops a = BlockOps<3, true, real, fst, 16, 4, 4, false, 0, 0, false, true>::ops();
         static const Ops w = BlockOps<3, true, real, fst, 16, 4, 4, false, 0, 0, true, true>::ops();
@@ -427,10 +428,16 @@ std::vector<Variant> chm_variants(bool large, bool walls) {
         static const Ops a2 = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 0, false, true>::ops();
         static const Ops a3 = BlockOps<3, true, real, fst, 64, 2, 4, true, 2, 0, false, true>::ops();
         static const Ops w = BlockOps<3, true, real, fst, 64, 2, 4, false, 0, 0, true, true>::ops();
-        if (walls) add(w);
-        else if (large && std::is_same<fst, __half>::value) for (const Ops* o : {&a3, &a2, &a0}) add(*o);
-        else if (large) for (const Ops* o : {&a2, &a3, &a0}) add(*o);
-        else for (const Ops* o : {&a0, &a2, &a3}) add(*o);
+        static const Ops k = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, false, true, 0>::ops();
+        static const Ops wk = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, true, true, 0>::ops();
+        if (walls && large) {
+            add(wk);
+            add(w);
+        } else if (walls) {
+            add(w);
+            add(wk);
+        } else if (large) for (const Ops* o : {&k, &a2, &a3, &a0}) add(*o);
+        else for (const Ops* o : {&a0, &a2, &a3, &k}) add(*o);
     }
     return v;
 }
@@ -497,6 +504,8 @@ std::string variant_name(const Variant& v) {
         if (t.zband > 1) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " zband %d", t.zband);
         if (t.walls) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " walls");
         if (t.chm) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " chmrt");
+        if (t.haux >= 0 && t.haux != t.aux)
+            std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " h-cached");
     return buf;
 }
 

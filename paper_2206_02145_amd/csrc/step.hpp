@@ -139,12 +139,17 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 //
 // WALLS: honour the solid-wall mask I.wall (zero-flux / no-slip bounce-back, see lbcg_set_walls).
 //
+// HAUX: cache-policy bits of the h stores (-1: AUX). h is read again by the next step with its halo
+// (each row by three tiles), while g, f and phi_prev are read once per step: with HAUX = 0, AUX = 2
+// and LAUX = 2 only h and phi_prev take room in the L2 and last-level caches, whose 256 MB then hold
+// the h planes between the steps (on the 192 x 128 x 128 flow grid: 160.7 instead of 184.6 us).
+//
 // Tile order: x fastest, so that the x-neighbours, which share the halo's cache lines, run
 // together. With I.zband = B > 1 the z tile-layers are grouped in bands of B: within a band the
 // order is x, then z, then y, so the tiles above and below run B * tiles_x apart instead of a whole
 // layer apart and the z-halo of h is still in L2 when it is read again.
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
-          int LAUX = 0, bool WALLS = false, bool CHM = false>
+          int LAUX = 0, bool WALLS = false, bool CHM = false, int HAUX = -1>
 __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, const int par) {
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
@@ -179,7 +184,8 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     }
     const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * TZ;
 
-    const Planes<real, AUX> hin(pick(I.h, par), I.Np), hout(pick(I.h, par ^ 1), I.Np);
+    constexpr int HA = HAUX < 0 ? AUX : HAUX;
+    const Planes<real, HA> hin(pick(I.h, par), I.Np), hout(pick(I.h, par ^ 1), I.Np);
     const Planes<real, AUX, LAUX> gin(pick(I.g, par), I.Np), gout(pick(I.g, par ^ 1), I.Np);
     const Planes<real, 0, LAUX> pprev(I.phi_prev, I.Nm);
     const Planes<fst, AUX, LAUX> fin(pick(I.f, par), I.Np), fout(pick(I.f, par ^ 1), I.Np);
@@ -574,15 +580,15 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
 }
 
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX,
-          bool WALLS = false, bool CHM = false>
+          bool WALLS = false, bool CHM = false, int HAUX = -1>
 __global__ __launch_bounds__(TX* TY* TZ) void step_single(InstDev I, int par) {
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM>(I, xcd_tile(blockIdx.x, gridDim.x), par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM, HAUX>(I, xcd_tile(blockIdx.x, gridDim.x), par);
 }
 
 // Batched launch: the tiles of all instances form one list; each workgroup finds its instance
 // by binary search over the tile offsets.
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX = 0,
-          bool CHM = false>
+          bool CHM = false, int HAUX = -1>
 __global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restrict__ insts, int ninst,
                                                          int par) {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -601,7 +607,7 @@ __global__ __launch_bounds__(TX* TY* TZ) void step_batch(const InstDev* __restri
     for (int k = 0; k < (int)(sizeof(InstDev) / 4); k++) w[k] = __builtin_amdgcn_readfirstlane(src[k]);
     InstDev I;
     __builtin_memcpy(&I, w, sizeof(InstDev));
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, false, CHM>(I, t - I.tile_begin, par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, false, CHM, HAUX>(I, t - I.tile_begin, par);
 }
 
 }  // namespace lbcg
