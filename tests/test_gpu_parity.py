@@ -425,7 +425,7 @@ def test_batch_matches_single_instances_bitwise(lb, use_graph):
     assert hist.shape == (3, len(plist), 16) and b.nstep == 307
     for i, p in enumerate(plist):
         s = lb.Solver(p, "fp32")
-        s.select_variant(s.variants().index("block 64x4x1 nt-stores"))  # the batch's tiling
+        s.select_variant(s.variants().index(b.variants()[b.variant]))  # the batch's tiling
         Ls = []
         for _ in range(3):
             s.step(100)
