@@ -140,9 +140,9 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 // WALLS: honour the solid-wall mask I.wall (zero-flux / no-slip bounce-back, see lbcg_set_walls).
 //
 // HAUX: cache-policy bits of the h stores (-1: AUX). h is read again by the next step with its halo
-// (each row by three tiles), while g, f and phi_prev are read once per step: with HAUX = 0, AUX = 2
-// and LAUX = 2 only h and phi_prev take room in the L2 and last-level caches, whose 256 MB then hold
-// the h planes between the steps (on the 192 x 128 x 128 flow grid: 160.7 instead of 184.6 us).
+// (each row by three tiles), while g and f are read once per step: with HAUX = 0, AUX = 2 and
+// LAUX = 2 only h and phi_prev take room in the L2 and last-level caches, whose 256 MB then hold
+// them between the steps (on the 192 x 128 x 128 flow grid: 158.8 instead of 184.6 us).
 //
 // Tile order: x fastest, so that the x-neighbours, which share the halo's cache lines, run
 // together. With I.zband = B > 1 the z tile-layers are grouped in bands of B: within a band the
@@ -187,7 +187,8 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
     constexpr int HA = HAUX < 0 ? AUX : HAUX;
     const Planes<real, HA> hin(pick(I.h, par), I.Np), hout(pick(I.h, par ^ 1), I.Np);
     const Planes<real, AUX, LAUX> gin(pick(I.g, par), I.Np), gout(pick(I.g, par ^ 1), I.Np);
-    const Planes<real, 0, LAUX> pprev(I.phi_prev, I.Nm);
+    // phi_prev (one plane, re-read by its own node the next step) stays cacheable with h
+    const Planes<real, 0, (HAUX == 0 ? 0 : LAUX)> pprev(I.phi_prev, I.Nm);
     const Planes<fst, AUX, LAUX> fin(pick(I.f, par), I.Np), fout(pick(I.f, par ^ 1), I.Np);
     // node (row + col) of plane a; with ROW the row is wave-uniform
     auto LD = [&](const auto& P, int a, unsigned row, int col) -> real {

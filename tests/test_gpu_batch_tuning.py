@@ -92,3 +92,33 @@ def test_batch_variant_timer_runs_real_steps_and_tuning_is_cached(lb):
     g = lb.Batch(plist, "fp32")
     assert g.variant == 0
     g.close()
+
+
+def test_tuning_cache_file_carries_the_choice_to_another_process(lb, tmp_path):
+    """With LBCG_TUNE_CACHE naming a file, a choice made in one process is read back by the next:
+    its first batch of the same mix of shapes starts on the tuned tiling."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.txt"
+    prog = (
+        "import sys; sys.path.insert(0, {root!r})\n"
+        "from paper_2206_02145_amd import lbcg, workloads as W\n"
+        "draws = W.sweep_draws(3, seed=3)\n"
+        "b = lbcg.Batch([W.sweep_instance(96, *d[1:]) for d in draws], 'fp32')\n"
+        "if sys.argv[1] == 'tune':\n"
+        "    best, us, _ = b.autotune(2)\n"
+        "    print('CHOICE', b.variants()[best])\n"
+        "else:\n"
+        "    print('CHOICE', b.variants()[b.variant])\n"
+        "b.close()\n").format(root=root)
+    env = dict(os.environ, LBCG_TUNE_CACHE=str(cache))
+    out = []
+    for mode in ("tune", "use"):
+        r = subprocess.run([sys.executable, "-c", prog, mode], env=env, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        out.append([l for l in r.stdout.splitlines() if l.startswith("CHOICE")][-1])
+    print("[tuning]", out, cache.read_text().strip(), flush=True)
+    assert out[0] == out[1]
+    assert "batch gfx" in cache.read_text() and out[0].split(" ", 1)[1] in cache.read_text()

@@ -5,8 +5,9 @@ through the seed centre and 8192 random nodes).
 
 Pointwise bar (binary32): max |error| over the samples divided by max |value| over the whole grid,
 1e-4 per field. The 192x128x128 case is checked pointwise at 4000 steps only: with eps = 0.05
-(above 1/35, so the interface stiffness 1 - 35 eps cos 6 theta is negative near the axes) the
-interface shape amplifies any perturbation, rounding included, by about 20x per 2000 steps
+the interface stiffness of Eq. (a), a^2 + (a^2)'' = 1 - 72 eps cos 6 theta to first order, is
+strongly negative near the axes (-2.6), and the interface shape amplifies any perturbation,
+rounding included, by about 20x per 2000 steps
 from step 4000 on, so two correct runs that round differently part pointwise (binary32 against
 binary64 on the GPU: phi 1.4e-5 at 4000 steps, 1e-2 at 8000, 0.24 at 20000). After 20000 steps
 the test checks what that amplification leaves alone: the solid volume, the crystal extents and
@@ -134,8 +135,9 @@ def test_full_length_flow_fp64(lb):
     s.close()
 
 
-# Binary32 against the oracle on the 96x64x64 flow grid at eps = 0.02 (interface stiffness positive:
-# no amplification of rounding), per snapshot. phi, rho and u stay within 1e-4 through the
+# Binary32 against the oracle on the 96x64x64 flow grid at eps = 0.02 (stiffness 1 - 72 eps cos 6 theta
+# only mildly negative near the axes, -0.44: no amplification of rounding seen within 20000 steps),
+# per snapshot. phi, rho and u stay within 1e-4 through the
 # 20000 steps. U meets 1e-4 through 8000 steps; after that its error grows about linearly in the
 # crystal, where q = 1 - phi = 0 makes tau_U exactly 1/2 and the solute's non-equilibrium mode is
 # undamped, so the last-place noise of phi = sum h that reaches it through the source -dphi/dt

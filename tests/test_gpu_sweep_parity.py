@@ -7,9 +7,10 @@ Bar: per field, max |error| over the sampled nodes / max |value| over the grid (
 the velocity u* as a vector over its largest component).
 
 * binary64, at the sweep's eps = 0.05: 1e-8 (the same algorithm; measured <= 1e-9).
-* binary32 at eps = 0.02 (interface stiffness 1 - 35 eps cos 6 theta positive): 1e-4, and the
+* binary32 at eps = 0.02 (interface stiffness 1 - 72 eps cos 6 theta only mildly negative near the
+  axes, -0.44, where no amplification shows within 4000 steps): 1e-4, and the
   crystal extents within 1e-3 cells, with every tiling of the batched step.
-* binary32 at eps = 0.05: the negative stiffness near the crystal axes amplifies any perturbation,
+* binary32 at eps = 0.05: the strongly negative stiffness near the crystal axes (-2.6) amplifies any perturbation,
   rounding included, about threefold per 500 steps once the crystal has grown (binary32 against
   binary64 on the GPU, instance 1: phi 1.5e-6 at 1000 steps, 6.5e-6 at 2000, 6.0e-5 at 3000,
   6.0e-4 at 4000), and a seed that melts (instance 8) vanishes a few steps earlier or later;

@@ -424,6 +424,35 @@ def test_allen_cahn_shrinking(orc, dim):
 # Exact discrete invariant (R8, P-j) and symmetries (P-k)
 # --------------------------------------------------------------------------------------------
 
+def test_anisotropic_shrinking_follows_the_interface_stiffness(orc):
+    """Thin-interface limit of Eq. (a) at lambda = 0 (Allen-Cahn with the anisotropy as written:
+    tau0 a^2 dphi/dt = W0^2 div(a^2 grad phi) + W0^2 div(|grad phi|^2 d(a^2)/d(grad phi)) + ...).
+    For a circle of radius R the equation gives, along the normal angle theta, the shrinking speed
+    (W0^2 / tau0) (A + A'') / (A R) with A = a_s(theta)^2 (the second term contributes A'' times the
+    curvature). With a_s = 1 + eps cos 6 theta: (A + A'')/A = 1 - 72 eps / (1 + eps) along the axes
+    and 1 + 72 eps / (1 - eps) at 30 degrees. Measured on a large circle early on (before the shape
+    departs from it), each direction's speed divided by the same direction's speed at eps = 0 (which
+    removes the lattice's own anisotropy and the finite-width corrections). A flux of half its size
+    would give 0.82 and 1.18, the gradient without its 1/cs^2 0.88 and 1.12, the opposite sign 1.36
+    and 0.64."""
+    n, R0, eps = 320, 120.0, 0.005
+    dirs = W.directions(12)  # 0, 30, ... degrees
+    v = {}
+    for e in (0.0, eps):
+        p = W.params(dim=2, nx=n, ny=n, lam=0.0, eps=e, U0=0.0, U_in=0.0, seed_c=(n / 2, n / 2, 0), seed_R=R0)
+        s = orc.Sim(p)
+        s.step(60)
+        L0 = s.measure(dirs)[0]
+        s.step(180)
+        L1 = s.measure(dirs)[0]
+        v[e] = (L0 - L1) / 180
+    axis = v[eps][0::2] / v[0.0][0::2]       # 0, 60, 120, ... degrees
+    diag = v[eps][1::2] / v[0.0][1::2]       # 30, 90, ... degrees
+    pa, pd = 1 - 72 * eps / (1 + eps), 1 + 72 * eps / (1 - eps)
+    print(f"axis {axis.mean():.3f} (predicted {pa:.3f}), 30 degrees {diag.mean():.3f} (predicted {pd:.3f})")
+    assert np.abs(axis - pa).max() < 0.05 and np.abs(diag - pd).max() < 0.06, (axis, diag)
+
+
 @pytest.mark.parametrize("dim,flow", [(2, 0), (2, 1), (3, 0)])
 def test_solute_plus_solid_invariant(orc, dim, flow):
     n = 48 if dim == 2 else 24
