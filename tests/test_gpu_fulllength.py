@@ -137,13 +137,16 @@ def test_full_length_flow_fp64(lb):
 
 # Binary32 against the oracle on the 96x64x64 flow grid at eps = 0.02 (stiffness 1 - 72 eps cos 6 theta
 # only mildly negative near the axes, -0.44: no amplification of rounding seen within 20000 steps),
-# per snapshot. phi, rho and u stay within 1e-4 through the
-# 20000 steps. U meets 1e-4 through 8000 steps; after that its error grows about linearly in the
-# crystal, where q = 1 - phi = 0 makes tau_U exactly 1/2 and the solute's non-equilibrium mode is
-# undamped, so the last-place noise of phi = sum h that reaches it through the source -dphi/dt
-# accumulates (measured against the oracle: 1.7e-5, 4.9e-5, 1.2e-4, 2.0e-4 and 2.5e-4 at
-# 4000 .. 20000 steps; 2.3e-4 at 8000 and 9.3e-4 at 20000 without the compensated closure of the
-# phase-field collision).
+# per snapshot. phi, rho and u stay within 1e-4 through the 20000 steps, and so does U on every
+# sampled node outside the crystal (oracle phi < 0.9: the liquid and the interface, where U enters
+# the phase field through lambda U (1 - phi^2)^2 and sets the growth). Inside the crystal
+# q = 1 - phi = 0 makes tau_U exactly 1/2: the solute lattice there has no diffusion and its
+# non-equilibrium modes are not damped, so every rounding that reaches it stays in the field, above
+# all the last-place noise of psi = phi + 1 ~ 2 that enters through the source -dphi/dt (binary32
+# against binary64 on the GPU after 20000 steps: U off by 6e-5 at crystal nodes where phi is off by
+# 1e-7, 1e-6 in the liquid and at the interface). U over all samples, crystal included, against the oracle:
+# 1.7e-5, 4.9e-5, 1.2e-4, 2.0e-4 and 2.5e-4 at 4000 .. 20000 steps (2.3e-4 at 8000 and 9.3e-4 at
+# 20000 without the compensated closure of the phase-field collision).
 C3R_U_BAR = {4000: 1e-4, 8000: 1e-4, 12000: 1.6e-4, 16000: 2.6e-4, 20000: 3.2e-4}
 
 
@@ -161,8 +164,14 @@ def test_reduced_flow_grid_every_4000_steps(lb, prec):
         done = step
         z = snaps[step]
         errs = errors(s, z, p)
+        nz_, ny_, nx_ = z["nodes"][:, 0], z["nodes"][:, 1], z["nodes"][:, 2]
+        outside = z["phi"] < 0.9  # liquid and interface nodes, by the oracle's phi
+        assert outside.sum() > 1000 and (~outside).sum() > 100
+        dU = np.abs(s.read("U")[nz_, ny_, nx_] - z["U"]) / z["absmax_U"]
+        errs["U_outside_crystal"] = float(dU[outside].max())
         dL, dVs, dM = aggregates(s, z)
         print(f"[fulllength] c3r {prec} @{step}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
+              f"; U in the crystal {float(dU[~outside].max()):.2e}"
               f"; max |dL| {dL:.2e} cells; Vs {dVs:.2e}; M' {dM:.2e}", flush=True)
         if prec == "fp64":
             for k, v in errs.items():
