@@ -22,6 +22,7 @@ struct Tiling {
     bool walls = false;  // the kernel honours the solid-wall mask
     bool chm = false;    // central-Hermite MRT flow collision
     int haux = -1;       // cache policy of the h stores (-1: aux)
+    int gcache = 0;      // with haux = 0: planes of g that keep the default policy as well
 };
 
 // One compiled tiling of the batched step (every instance's tiles in one launch) and its

@@ -281,12 +281,12 @@ struct CommonOps {
 };
 
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
-          int LAUX = 0, bool WALLS = false, bool CHM = false, int HAUX = -1>
+          int LAUX = 0, bool WALLS = false, bool CHM = false, int HAUX = -1, int GC = 0>
 struct BlockOps : CommonOps<DIM, FLOW, real, fst> {
     using C = CommonOps<DIM, FLOW, real, fst>;
     static void step(const InstDev& I, int par, hipStream_t s) {
         const int nblocks = I.tiles_x * I.tiles_y * I.tiles_z;
-        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM, HAUX>),
+        hipLaunchKernelGGL((step_single<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM, HAUX, GC>),
                            dim3(nblocks), dim3(TX * TY * TZ), 0, s, I, par);
     }
     static Ops ops() {
@@ -294,6 +294,7 @@ struct BlockOps : CommonOps<DIM, FLOW, real, fst> {
         t.walls = WALLS;
         t.chm = CHM;
         t.haux = HAUX;
+        t.gcache = HAUX == 0 ? GC : 0;
         return Ops{t, step, C::init, C::field, C::reduce, C::ray};
     }
 };
@@ -331,7 +332,7 @@ constexpr int MARCH_MAX_NX = 256;
 constexpr double LLC_BYTES = 256.0 * 1024 * 1024;
 
 template <int DIM, bool FLOW, typename real, typename fst>
-void block_variants(std::vector<Variant>& v, bool large) {
+void block_variants(std::vector<Variant>& v, bool large, int gdef) {
     auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
     if constexpr (DIM == 2) {
         static const Ops a = BlockOps<2, FLOW, real, fst, 64, 4, 1, false, sizeof(real) == 8 ? 0 : 2>::ops();
@@ -367,17 +368,26 @@ void block_variants(std::vector<Variant>& v, bool large) {
         static const Ops d0 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2>::ops();
         // streaming loads and stores of g, f and phi_prev, h kept in the caches (see step_tile)
         static const Ops k0 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, false, false, 0>::ops();
+        // the same with 2 or 3 planes of g kept in the caches as well
+        static const Ops k2 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, false, false, 0, 2>::ops();
+        static const Ops k3 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, false, false, 0, 3>::ops();
+        const Ops* kd = gdef >= 3 ? &k3 : (gdef == 2 ? &k2 : &k0);
         auto band = [&](const Ops& o, int zband) {  // the same kernel with a banded tile order
             Tiling t = o.tiling;
             t.zband = zband;
             v.push_back({&o, t});
         };
         // first = default: 64 x 2 x 4 (one wavefront per x-row); when the two population copies
-        // exceed the last-level cache, streaming loads and stores of g, f and phi_prev with h kept in
-        // the caches (the fastest measured on the 192 x 128 x 128 flow grid, also with binary16
-        // flow storage); below that size, the default policy everywhere
-        if (large) for (const Ops* o : {&k0, &a2, &a3, &a0, &a1, &d0}) add(*o);
-        else for (const Ops* o : {&a0, &a1, &a2, &a3, &d0, &k0}) add(*o);
+        // exceed the last-level cache, streaming loads and stores of g and f with h and phi_prev
+        // kept in the caches, and gdef planes of g with them (the fastest measured on the
+        // 192 x 128 x 128 flow grid, also with binary16 flow storage); below that size, the
+        // default policy everywhere
+        if (large) {
+            add(*kd);
+            for (const Ops* o : {&k0, &k2, &k3})
+                if (o != kd) add(*o);
+            for (const Ops* o : {&a2, &a3, &a0, &a1, &d0}) add(*o);
+        } else for (const Ops* o : {&a0, &a1, &a2, &a3, &d0, &k0, &k2, &k3}) add(*o);
         for (int zb : {2, 4, 8}) band(large ? a2 : a0, zb);
         band(large ? a3 : a1, 4);
         for (const Ops* o : {&b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
@@ -386,7 +396,7 @@ void block_variants(std::vector<Variant>& v, bool large) {
 
 // Tilings of the kernel that honours a wall mask (the first is the default).
 template <int DIM, bool FLOW, typename real, typename fst>
-std::vector<Variant> wall_variants(bool large) {
+std::vector<Variant> wall_variants(bool large, int gdef) {
     std::vector<Variant> v;
     auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
     if constexpr (DIM == 2) {
@@ -399,15 +409,17 @@ std::vector<Variant> wall_variants(bool large) {
         static const Ops a = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 0, 0, true>::ops();
         static const Ops b = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 0, true>::ops();
         static const Ops k = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, true, false, 0>::ops();
-        if (large) for (const Ops* o : {&k, &b, &a}) add(*o);
-        else for (const Ops* o : {&a, &b, &k}) add(*o);
+        static const Ops k2 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, true, false, 0, 2>::ops();
+        if (large && gdef >= 2) for (const Ops* o : {&k2, &k, &b, &a}) add(*o);
+        else if (large) for (const Ops* o : {&k, &k2, &b, &a}) add(*o);
+        else for (const Ops* o : {&a, &b, &k, &k2}) add(*o);
     }
     return v;
 }
 
 // Tilings of the central-Hermite MRT flow kernel, with or without walls (the first is the default).
 template <int DIM, typename real, typename fst>
-std::vector<Variant> chm_variants(bool large, bool walls) {
+std::vector<Variant> chm_variants(bool large, bool walls, int gdef) {
     std::vector<Variant> v;
     auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
     if constexpr (DIM == 2) {
@@ -429,6 +441,7 @@ std::vector<Variant> chm_variants(bool large, bool walls) {
         static const Ops a3 = BlockOps<3, true, real, fst, 64, 2, 4, true, 2, 0, false, true>::ops();
         static const Ops w = BlockOps<3, true, real, fst, 64, 2, 4, false, 0, 0, true, true>::ops();
         static const Ops k = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, false, true, 0>::ops();
+        static const Ops k2 = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, false, true, 0, 2>::ops();
         static const Ops wk = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, true, true, 0>::ops();
         if (walls && large) {
             add(wk);
@@ -436,20 +449,21 @@ std::vector<Variant> chm_variants(bool large, bool walls) {
         } else if (walls) {
             add(w);
             add(wk);
-        } else if (large) for (const Ops* o : {&k, &a2, &a3, &a0}) add(*o);
-        else for (const Ops* o : {&a0, &a2, &a3, &k}) add(*o);
+        } else if (large && gdef >= 2) for (const Ops* o : {&k2, &k, &a2, &a3, &a0}) add(*o);
+        else if (large) for (const Ops* o : {&k, &k2, &a2, &a3, &a0}) add(*o);
+        else for (const Ops* o : {&a0, &a2, &a3, &k, &k2}) add(*o);
     }
     return v;
 }
 
 template <int DIM, bool FLOW, typename real, typename fst>
-std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls, bool chm) {
+std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls, bool chm, int gdef) {
     if constexpr (FLOW) {
-        if (chm) return chm_variants<DIM, real, fst>(pop_bytes > LLC_BYTES, walls);
+        if (chm) return chm_variants<DIM, real, fst>(pop_bytes > LLC_BYTES, walls, gdef);
     }
-    if (walls) return wall_variants<DIM, FLOW, real, fst>(pop_bytes > LLC_BYTES);
+    if (walls) return wall_variants<DIM, FLOW, real, fst>(pop_bytes > LLC_BYTES, gdef);
     std::vector<Variant> v;
-    block_variants<DIM, FLOW, real, fst>(v, pop_bytes > LLC_BYTES);
+    block_variants<DIM, FLOW, real, fst>(v, pop_bytes > LLC_BYTES, gdef);
     if constexpr (DIM == 3) {
         if (nx > 0 && nx <= MARCH_MAX_NX) {  // (nx = 0: not offered)
             // z-marching kernels (rows of up to 256 nodes) as further candidates
@@ -473,19 +487,35 @@ std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls, bool chm)
     return v;
 }
 
-// Candidate tilings for one grid kind; the first is the default. pop_bytes: both population copies.
-std::vector<Variant> variants_for(int dim, int flow, int prec, int nx, double pop_bytes, bool walls, bool chm) {
+// Candidate tilings for one grid kind; the first is the default. pop_bytes: both population copies;
+// gdef: planes of g the default keeps in the caches beside h and phi_prev (default_gcache).
+std::vector<Variant> variants_for(int dim, int flow, int prec, int nx, double pop_bytes, bool walls, bool chm,
+                                  int gdef) {
     const double b = pop_bytes;
+    const int g = gdef;
     if (dim == 2) {
-        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx, b, walls, false) : variants_of<2, false, float, float>(nx, b, walls, false);
-        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx, b, walls, chm)
-               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx, b, walls, chm)
-                                   : variants_of<2, true, float, __half>(nx, b, walls, chm);
+        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx, b, walls, false, g) : variants_of<2, false, float, float>(nx, b, walls, false, g);
+        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx, b, walls, chm, g)
+               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx, b, walls, chm, g)
+                                   : variants_of<2, true, float, __half>(nx, b, walls, chm, g);
     }
-    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx, b, walls, false) : variants_of<3, false, float, float>(nx, b, walls, false);
-    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx, b, walls, chm)
-           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx, b, walls, chm)
-                               : variants_of<3, true, float, __half>(nx, b, walls, chm);
+    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx, b, walls, false, g) : variants_of<3, false, float, float>(nx, b, walls, false, g);
+    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx, b, walls, chm, g)
+           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx, b, walls, chm, g)
+                               : variants_of<3, true, float, __half>(nx, b, walls, chm, g);
+}
+
+// What the step keeps in the caches between steps (h, phi_prev and the first planes of g) pays only
+// while it fits well inside the 256 MB last-level cache: on the 192 x 128 x 128 flow grid 10 planes
+// (126 MB) gained 3.8 %, 11 (138 MB) 5.3 %, 12 (151 MB) lost 2 %, and on 256 x 128 x 128 a ninth
+// plane (151 MB) lost 4 %. The default keeps 3 or 2 planes of g when everything kept stays within
+// 128 MiB, else none; the autotuner can choose otherwise.
+constexpr double CACHE_KEEP_BYTES = 128.0 * 1024 * 1024;
+int default_gcache(const lbcg_params& p) {
+    const double plane = (double)stored_nodes(&p) * real_size(p.precision);
+    for (int k : {3, 2})
+        if ((qs_of(p.dim) + 1 + k) * plane <= CACHE_KEEP_BYTES) return k;
+    return 0;
 }
 
 double population_bytes(const lbcg_params& p) {
@@ -506,6 +536,7 @@ std::string variant_name(const Variant& v) {
         if (t.chm) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " chmrt");
         if (t.haux >= 0 && t.haux != t.aux)
             std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " h-cached");
+        if (t.gcache > 0) std::snprintf(buf + std::strlen(buf), sizeof buf - std::strlen(buf), " g%d-cached", t.gcache);
     return buf;
 }
 
@@ -786,7 +817,7 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
         const bool chm = p->collision == LBCG_COLLISION_CHMRT;
         hdl->variants = variants_for(p->dim, p->flow, p->precision,
                                      (p->xbc == LBCG_INFLOW_PRESSURE || chm) ? 0 : p->nx,  // (0: no z-marching tiling)
-                                     population_bytes(*p), p->walls != 0, chm);
+                                     population_bytes(*p), p->walls != 0, chm, default_gcache(*p));
         hdl->variant = 0;
         std::string tuned;  // a tiling the autotuner chose for this grid earlier in the process
         if (tune_lookup(grid_key(*p), tuned)) hdl->variant = std::max(0, variant_index_by_name(hdl->variants, tuned));
@@ -1419,7 +1450,7 @@ lbcg_status lbcg_batch_create(int n, const lbcg_params* p, void* dev_workspace, 
             for (int k = 0; k < (int)b->kits->size(); k++)
                 if (variant_name(Variant{nullptr, (*b->kits)[k].tiling}) == tuned) b->kit_idx = k;
         b->kit = &(*b->kits)[b->kit_idx];
-        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0, false, false)[0].ops;
+        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0, false, false, 0)[0].ops;
         b->par = 0;
         b->nstep = 0;
         int tiles = 0;

@@ -52,8 +52,9 @@ template <> struct BufOps<__half> {
 };
 
 // q planes of N values of storage type T; loads convert to the compute type R. Stores use the
-// cache-policy bits AUX, loads LAUX.
-template <typename T, int AUX = 0, int LAUX = 0> struct Planes {
+// cache-policy bits AUX, loads LAUX, except for the first KC planes, which keep the default policy
+// for both (the plane index is a compile-time constant after unrolling, so the choice folds away).
+template <typename T, int AUX = 0, int LAUX = 0, int KC = 0> struct Planes {
     const char* base;
     unsigned plane_bytes;  // N * sizeof(T), < 2^32
 
@@ -63,33 +64,41 @@ template <typename T, int AUX = 0, int LAUX = 0> struct Planes {
         return __builtin_amdgcn_make_buffer_rsrc((void*)(base + (size_t)a * plane_bytes), (short)0,
                                                  (int)plane_bytes, BUF_RSRC_WORD3);
     }
+    __device__ __forceinline__ T raw_ld(int a, unsigned off, unsigned soff) const {
+        if (a < KC) return BufOps<T>::template ld<0>(rsrc(a), off, soff);
+        return BufOps<T>::template ld<LAUX>(rsrc(a), off, soff);
+    }
+    __device__ __forceinline__ void raw_st(int a, unsigned off, T v, unsigned soff) const {
+        if (a < KC) BufOps<T>::template st<0>(rsrc(a), off, v, soff);
+        else BufOps<T>::template st<AUX>(rsrc(a), off, v, soff);
+    }
     template <typename R> __device__ __forceinline__ R ld(int a, unsigned node) const {
         if constexpr (std::is_same<T, __half>::value)
-            return (R)__half2float(BufOps<T>::template ld<LAUX>(rsrc(a), node * 2u));
+            return (R)__half2float(raw_ld(a, node * 2u, 0));
         else
-            return (R)BufOps<T>::template ld<LAUX>(rsrc(a), node * (unsigned)sizeof(T));
+            return (R)raw_ld(a, node * (unsigned)sizeof(T), 0);
     }
     template <typename R> __device__ __forceinline__ void st(int a, unsigned node, R v) const {
         if constexpr (std::is_same<T, __half>::value)
-            BufOps<T>::template st<AUX>(rsrc(a), node * 2u, __float2half_rn((float)v));
+            raw_st(a, node * 2u, __float2half_rn((float)v), 0);
         else
-            BufOps<T>::template st<AUX>(rsrc(a), node * (unsigned)sizeof(T), (T)v);
+            raw_st(a, node * (unsigned)sizeof(T), (T)v, 0);
     }
     // Node row + col where `row` is the same for the whole wavefront: it travels in the scalar
     // offset of the buffer instruction, and the lane supplies only its column.
     template <typename R> __device__ __forceinline__ R ldr(int a, unsigned row, unsigned col) const {
         constexpr unsigned B = sizeof(T);
         if constexpr (std::is_same<T, __half>::value)
-            return (R)__half2float(BufOps<T>::template ld<LAUX>(rsrc(a), col * B, row * B));
+            return (R)__half2float(raw_ld(a, col * B, row * B));
         else
-            return (R)BufOps<T>::template ld<LAUX>(rsrc(a), col * B, row * B);
+            return (R)raw_ld(a, col * B, row * B);
     }
     template <typename R> __device__ __forceinline__ void str(int a, unsigned row, unsigned col, R v) const {
         constexpr unsigned B = sizeof(T);
         if constexpr (std::is_same<T, __half>::value)
-            BufOps<T>::template st<AUX>(rsrc(a), col * B, __float2half_rn((float)v), row * B);
+            raw_st(a, col * B, __float2half_rn((float)v), row * B);
         else
-            BufOps<T>::template st<AUX>(rsrc(a), col * B, (T)v, row * B);
+            raw_st(a, col * B, (T)v, row * B);
     }
 };
 

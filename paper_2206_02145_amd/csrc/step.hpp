@@ -143,13 +143,16 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks) {
 // (each row by three tiles), while g and f are read once per step: with HAUX = 0, AUX = 2 and
 // LAUX = 2 only h and phi_prev take room in the L2 and last-level caches, whose 256 MB then hold
 // them between the steps (on the 192 x 128 x 128 flow grid: 158.8 instead of 184.6 us).
+// GC (with HAUX = 0): the first GC planes of g keep the default policy too, so that the next step
+// reads them from the last-level cache as well; that pays while everything kept there stays below
+// about 128 MiB (on the same grid, 2 planes: 153.9 us, 3: 151.4 us, 4: 163.1 us).
 //
 // Tile order: x fastest, so that the x-neighbours, which share the halo's cache lines, run
 // together. With I.zband = B > 1 the z tile-layers are grouped in bands of B: within a band the
 // order is x, then z, then y, so the tiles above and below run B * tiles_x apart instead of a whole
 // layer apart and the z-halo of h is still in L2 when it is read again.
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF = false, int AUX = 0,
-          int LAUX = 0, bool WALLS = false, bool CHM = false, int HAUX = -1>
+          int LAUX = 0, bool WALLS = false, bool CHM = false, int HAUX = -1, int GC = 0>
 __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, const int par) {
     using S = typename Lattices<DIM>::S;
     using V = typename Lattices<DIM>::V;
@@ -186,7 +189,7 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
 
     constexpr int HA = HAUX < 0 ? AUX : HAUX;
     const Planes<real, HA> hin(pick(I.h, par), I.Np), hout(pick(I.h, par ^ 1), I.Np);
-    const Planes<real, AUX, LAUX> gin(pick(I.g, par), I.Np), gout(pick(I.g, par ^ 1), I.Np);
+    const Planes<real, AUX, LAUX, (HAUX == 0 ? GC : 0)> gin(pick(I.g, par), I.Np), gout(pick(I.g, par ^ 1), I.Np);
     // phi_prev (one plane, re-read by its own node the next step) stays cacheable with h
     const Planes<real, 0, (HAUX == 0 ? 0 : LAUX)> pprev(I.phi_prev, I.Nm);
     const Planes<fst, AUX, LAUX> fin(pick(I.f, par), I.Np), fout(pick(I.f, par ^ 1), I.Np);
@@ -581,9 +584,9 @@ __device__ __forceinline__ void step_tile(const InstDev& I, const int tile, cons
 }
 
 template <int DIM, bool FLOW, typename real, typename fst, int TX, int TY, int TZ, bool PF, int AUX, int LAUX,
-          bool WALLS = false, bool CHM = false, int HAUX = -1>
+          bool WALLS = false, bool CHM = false, int HAUX = -1, int GC = 0>
 __global__ __launch_bounds__(TX* TY* TZ) void step_single(InstDev I, int par) {
-    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM, HAUX>(I, xcd_tile(blockIdx.x, gridDim.x), par);
+    step_tile<DIM, FLOW, real, fst, TX, TY, TZ, PF, AUX, LAUX, WALLS, CHM, HAUX, GC>(I, xcd_tile(blockIdx.x, gridDim.x), par);
 }
 
 // Batched launch: the tiles of all instances form one list; each workgroup finds its instance
