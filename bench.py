@@ -6,13 +6,15 @@ seeded input. One step = one coupled time step of all three lattices (one fused 
 timed loop also runs the diagnostics (binary64 reductions + ray-march along 16 directions) every
 100 steps. value = whole-job MLUPS (nodes x steps / time).
 
-Also reported: the fused kernel's roofline (algorithmic bytes per launch / HIP-event launch time,
+Each single-grid case is autotuned first (every tiling timed on real steps of a throw-away solver of
+the same grid; the timed solver starts on the choice). Also reported: the fused kernel's roofline (algorithmic bytes per launch / HIP-event launch time,
 against the 8 TB/s HBM peak), HBM bytes from rocprofv3 counters when profiles/ holds them for the
 current kernel source, the binary16-shift variant, the no-flow 3-D grid, and the oracle timed on the
 host cores as a CPU baseline.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       python bench.py --profile-run            (short run for rocprofv3: step kernels, batched sweep,
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-tune] [--tune-file PATH]
+       python bench.py --profile-run [--tune-file PATH] [--profile-variants PATH]
+                                                (short run for rocprofv3: step kernels, batched sweep,
                                                  surrogate MLP, 1 GiB copy)
        python bench.py --summarize-profiles DIR (rocprofv3 csv output -> profiles/*.md, traffic.json)
 """
@@ -60,8 +62,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(name: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source."""
+def counter_traffic(name: str, variant: str | None = None):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source (and,
+    where the run recorded it, on this tiling)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -70,6 +73,8 @@ def counter_traffic(name: str):
         return None
     e = d.get(name)
     if not e or e.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if variant is not None and e.get("variant") not in (None, variant):
         return None
     return e.get("bytes_per_launch")
 
@@ -99,16 +104,36 @@ def median_ms(fn, reps: int = REPS):
     return statistics.median(fn() for _ in range(reps))
 
 
-def gpu_case(name, p, prec, steps, warmup, with_measure, walls=None):
+TUNE_LAUNCHES = 20  # timed steps per tiling and round of the autotuner
+
+
+def tune_grid(p, prec, walls=None):
+    """Autotune the step kernel for this grid on a throw-away solver (real steps of every tiling, two
+    rounds); the choice goes into the process's tuning cache, so the next solver of the grid starts
+    on it."""
+    from paper_2206_02145_amd import lbcg
+    s = lbcg.Solver(p, prec)
+    if walls is not None:
+        s.set_walls(walls)
+    s.step(2)
+    default = s.variants()[0]
+    best, us = s.autotune(TUNE_LAUNCHES)
+    chosen = s.variants()[best]
+    s.close()
+    return dict(default=default, chosen=chosen, chosen_us=round(us, 1))
+
+
+def gpu_case(name, p, prec, steps, warmup, with_measure, walls=None, tune=True):
     import torch
 
     from paper_2206_02145_amd import lbcg
     from paper_2206_02145_amd import workloads as W
     nodes = p["nx"] * p["ny"] * p["nz"]
+    tuning = tune_grid(p, prec, walls) if tune else None
     s = lbcg.Solver(p, prec)
     if walls is not None:
         s.set_walls(walls)
-    variant = s.variants()[s.variant]  # the default tiling (the fastest measured on MI355X)
+    variant = s.variants()[s.variant]  # the autotuner's choice (else the default tiling)
     dirs = W.directions(16, p["dim"])
     s.step(warmup)
     torch.cuda.synchronize()
@@ -129,9 +154,9 @@ def gpu_case(name, p, prec, steps, warmup, with_measure, walls=None):
                mlups=nodes * steps / (ms_job * 1e-3) / 1e6,
                kernel_ms=ms_kernel / steps, kernel_mlups=nodes / t_launch / 1e6,
                bytes_per_lup=bpl, achieved_gbs=achieved, frac=achieved / HBM_PEAK_GBS,
-               crystal_mean_L=float(L.mean()), nonfinite=mass["nonfinite"], variant=variant)
+               crystal_mean_L=float(L.mean()), nonfinite=mass["nonfinite"], variant=variant, tuning=tuning)
     log(f"{name}: {out['mlups']:.0f} MLUPS (job), kernel {out['kernel_ms']*1e3:.1f} us/step = "
-        f"{achieved:.0f} GB/s algorithmic ({out['frac']*100:.1f}% of {HBM_PEAK_GBS:.0f})")
+        f"{achieved:.0f} GB/s algorithmic ({out['frac']*100:.1f}% of {HBM_PEAK_GBS:.0f}); {variant}")
     return out
 
 
@@ -362,17 +387,29 @@ def summarize_profiles(d: str, out_dir: str = os.path.join(ROOT, "profiles")):
     cal["FETCH_SIZE"] = (COPY_BYTES / 1024) / st.mean(counters[("copy_1GiB", "FETCH_SIZE")])
     cal["WRITE_SIZE"] = (COPY_BYTES / 1024) / st.mean(counters[("copy_1GiB", "WRITE_SIZE")])
     alg_bytes = profile_workloads()
+    variants = {}
+    vpath = os.path.join(d, "variants.json")
+    if os.path.exists(vpath):
+        with open(vpath) as fh:
+            variants = json.load(fh)
     traffic = {}
-    head = ["Commands (from the repository root, TMPDIR=/tmp):", "",
-             f"    rocprofv3 --kernel-trace --stats -f csv -d {d}/prof_kt -o run -- python3 bench.py --profile-run",
-             f"    rocprofv3 --pmc FETCH_SIZE -f csv -d {d}/prof_fetch -o run -- python3 bench.py --profile-run",
-             f"    rocprofv3 --pmc WRITE_SIZE -f csv -d {d}/prof_write -o run -- python3 bench.py --profile-run",
-             f"    python3 bench.py --summarize-profiles {d}", "",
+    tf = f"--tune-file {d}/tune_cache.txt"
+    head = ["Commands (from the repository root, TMPDIR=/tmp; the first is the bench run whose autotuner "
+            "choices the profiled runs start on):", "",
+             f"    python3 bench.py {tf}",
+             f"    rocprofv3 --kernel-trace --stats -f csv -d {d}/prof_kt -o run -- python3 bench.py --profile-run {tf} "
+             f"--profile-variants {d}/variants.json",
+             f"    rocprofv3 --pmc FETCH_SIZE -f csv -d {d}/prof_fetch -o run -- python3 bench.py --profile-run {tf}",
+             f"    rocprofv3 --pmc WRITE_SIZE -f csv -d {d}/prof_write -o run -- python3 bench.py --profile-run {tf}",
+             f"    python3 bench.py --summarize-profiles {d}", ""]
+    if variants:
+        head += ["Profiled tilings: " + "; ".join(f"{k}: {v}" for k, v in sorted(variants.items())), ""]
+    head += [
              f"Counter calibration on a 1 GiB device copy: FETCH_SIZE x {cal['FETCH_SIZE']:.3f}, "
              f"WRITE_SIZE x {cal['WRITE_SIZE']:.3f} (true bytes / counted bytes). Algorithmic GB/s: "
              "algorithmic bytes of one launch / its average duration.", "",
-             "| kernel | calls | avg us | min us | max us | read MB | write MB | algorithmic MB | measured / algorithmic | GB/s (measured bytes) | GB/s (algorithmic) |",
-             "|---|---|---|---|---|---|---|---|---|---|---|"]
+             "| kernel | calls | avg us | median us | min us | max us | read MB | write MB | algorithmic MB | measured / algorithmic | GB/s (measured bytes) | GB/s (algorithmic) |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|"]
     table = {}
     for tag in sorted(stats):
         ts = stats[tag]
@@ -389,9 +426,11 @@ def summarize_profiles(d: str, out_dir: str = os.path.join(ROOT, "profiles")):
             ratio = f"{(rd_mb + wr_mb) * 1e6 / alg_b:.3f}"
             traffic[tag] = {"bytes_per_launch": round((rd_mb + wr_mb) * 1e6),
                             "read_bytes": round(rd_mb * 1e6), "write_bytes": round(wr_mb * 1e6),
-                            "avg_us": round(st.mean(ts), 2), "kernel_source_hash": kernel_source_hash()}
+                            "avg_us": round(st.mean(ts), 2), "median_us": round(st.median(ts), 2),
+                            "kernel_source_hash": kernel_source_hash(),
+                            "variant": variants.get(tag)}
         gbs = (rd_mb + wr_mb) * 1e6 / (st.mean(ts) * 1e-6) / 1e9 if fe and wr else float("nan")
-        table[tag] = (f"| {tag} | {len(ts)} | {st.mean(ts):.1f} | {min(ts):.1f} | {max(ts):.1f} | "
+        table[tag] = (f"| {tag} | {len(ts)} | {st.mean(ts):.1f} | {st.median(ts):.1f} | {min(ts):.1f} | {max(ts):.1f} | "
                       f"{rd_mb:.1f} | {wr_mb:.1f} | {alg} | {ratio} | {gbs:.0f} | {alg_gbs} |")
     os.makedirs(out_dir, exist_ok=True)
     for fname, title, keep in PROFILE_GROUPS:
@@ -427,7 +466,7 @@ def summarize_sq(d: str):
     lines = ["# rocprofv3 SQ counters: fused coupled step, 3-D 192x128x128 with flow (C3)", "",
              "Commands (from the repository root, TMPDIR=/tmp):", "",
              "    rocprofv3 --pmc " + " ".join(SQ_COUNTERS) +
-             f" -f csv -d {d}/prof_sq -o run -- python3 bench.py --profile-run",
+             f" -f csv -d {d}/prof_sq -o run -- python3 bench.py --profile-run --tune-file {d}/tune_cache.txt",
              f"    python3 bench.py --summarize-sq {d}", "",
              "Per wavefront (one wavefront = one 64-node row segment), mean over the dispatches:", "",
              "| kernel | waves | VALU | SALU | VMEM read | VMEM write | LDS | VALU busy (4 cycles / instruction) |",
@@ -459,6 +498,12 @@ def main():
     ap.add_argument("--surrogate-train", type=int, default=4096)
     ap.add_argument("--profile-run", action="store_true",
                     help="a short run of the headline kernel and a 1 GiB copy, for rocprofv3")
+    ap.add_argument("--no-tune", action="store_true", help="time the default tilings (no autotuning)")
+    ap.add_argument("--profile-variants", metavar="PATH",
+                    help="with --profile-run: write the tiling profiled for each kernel (JSON)")
+    ap.add_argument("--tune-file", metavar="PATH",
+                    help="tuning cache file: the autotuner's choices are appended to it, and solvers of a "
+                         "grid it already holds start on that choice (with --profile-run: the tilings profiled)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="summarise rocprofv3 csv output under DIR into profiles/")
     ap.add_argument("--summarize-sq", metavar="DIR", help="summarise the SQ-counter run under DIR/prof_sq")
@@ -473,6 +518,8 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this solver runs on a "
               f"single MI355X; a multi-GPU run would shard the grid into slabs)", file=sys.stderr)
         sys.exit(2)
+    if args.tune_file:  # read by the library at its first use of the tuning cache
+        os.environ["LBCG_TUNE_CACHE"] = os.path.abspath(args.tune_file)
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
@@ -484,19 +531,27 @@ def main():
 
     p3 = W.config3()
     if args.profile_run:
+        # every solver starts on the tiling the tuning file holds for its grid (a bench run with the
+        # same --tune-file chose it), else on the default; no autotuning here, so that the profile
+        # holds only the profiled tilings
         s = lbcg.Solver(p3, "fp32")
-        s.step(PROFILE_STEPS)
         s16 = lbcg.Solver(W.config3(), "fp16shift")
-        s16.step(PROFILE_STEPS)
         sm = lbcg.Solver(dict(W.config3(), collision=1, omega_bulk=1.0), "fp32")
-        sm.step(PROFILE_STEPS)
         s2 = lbcg.Solver(W.config2(), "fp32")
-        s2.step(PROFILE_STEPS)
+        bt = lbcg.Batch([W.sweep_instance(*d) for d in W.sweep_draws(256)], "fp32")
+        profiled = {"step_3d_flow_fp32": s, "step_3d_flow_fp16shift": s16, "step_3d_flow_chmrt_fp32": sm,
+                    "step_3d_noflow_fp32": s2, "step_batch_2d_flow_fp32": bt}
+        profiled = {k: x.variants()[x.variant] for k, x in profiled.items()}
+        log("profiled tilings: " + json.dumps(profiled))
+        if args.profile_variants:
+            with open(args.profile_variants, "w") as fh:
+                json.dump(profiled, fh, indent=1)
+        for x in (s, s16, sm, s2):
+            x.step(PROFILE_STEPS)
         torch.cuda.synchronize()
         for x in (s, s16, sm, s2):
             x.close()
         # the batched sweep (one step_batch launch per step, diagnostics every 100 steps, no graph)
-        bt = lbcg.Batch([W.sweep_instance(*d) for d in W.sweep_draws(256)], "fp32")
         bt.run(PROFILE_STEPS, MEASURE_EVERY, W.directions(16), use_graph=False)
         bt.close()
         # the surrogate MLP on synthetic rows of the sweep's shape: training steps, then a prediction
@@ -518,16 +573,20 @@ def main():
         log("profile run done")
         return
 
-    head = gpu_case("3-D flow 192x128x128 fp32", p3, "fp32", args.steps, args.warmup, True)
-    f16 = gpu_case("3-D flow 192x128x128 fp16shift", p3, "fp16shift", args.steps, args.warmup, False)
-    c2 = gpu_case("3-D no-flow 128^3 fp32", W.config2(), "fp32", args.steps, args.warmup, False)
+    tn = not args.no_tune
+    head = gpu_case("3-D flow 192x128x128 fp32", p3, "fp32", args.steps, args.warmup, True, tune=tn)
+    f16 = gpu_case("3-D flow 192x128x128 fp16shift", p3, "fp16shift", args.steps, args.warmup, False, tune=tn)
+    c2 = gpu_case("3-D no-flow 128^3 fp32", W.config2(), "fp32", args.steps, args.warmup, False, tune=tn)
     pw, mw = W.config3_walls()
-    c3w = gpu_case("3-D flow 192x128x128 fp32, walls and a baffle", pw, "fp32", args.steps, args.warmup, False, mw)
+    c3w = gpu_case("3-D flow 192x128x128 fp32, walls and a baffle", pw, "fp32", args.steps, args.warmup, False, mw,
+                   tune=tn)
     chm = gpu_case("3-D flow 192x128x128 fp32, central-Hermite MRT", dict(p3, collision=1, omega_bulk=1.0), "fp32",
-                   args.steps, args.warmup, False)
+                   args.steps, args.warmup, False, tune=tn)
     # rows of 191 nodes (764 B, stored at a pitch of 256 nodes) and planes of a power-of-two size
-    rag = gpu_case("3-D flow 191x128x128 fp32", W.scaled(p3, 191, 128, 128), "fp32", args.steps, args.warmup, False)
-    pw2 = gpu_case("3-D flow 256x128x128 fp32", W.scaled(p3, 256, 128, 128), "fp32", args.steps, args.warmup, False)
+    rag = gpu_case("3-D flow 191x128x128 fp32", W.scaled(p3, 191, 128, 128), "fp32", args.steps, args.warmup, False,
+                   tune=tn)
+    pw2 = gpu_case("3-D flow 256x128x128 fp32", W.scaled(p3, 256, 128, 128), "fp32", args.steps, args.warmup, False,
+                   tune=tn)
     sweep = None if args.no_sweep else sweep_case(args.sweep_n, args.sweep_steps, MEASURE_EVERY)
     surr = None
     if not args.no_surrogate:
@@ -539,9 +598,9 @@ def main():
     if cpu:
         log(f"cpu baseline: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads ({cpu['sample']})")
 
-    traffic = counter_traffic("step_3d_flow_fp32")
-    f16["traffic"] = counter_traffic("step_3d_flow_fp16shift")
-    c2["traffic"] = counter_traffic("step_3d_noflow_fp32")
+    traffic = counter_traffic("step_3d_flow_fp32", head["variant"])
+    f16["traffic"] = counter_traffic("step_3d_flow_fp16shift", f16["variant"])
+    c2["traffic"] = counter_traffic("step_3d_noflow_fp32", c2["variant"])
     rec = {
         "metric": "coupled-LB MLUPS & HBM-roofline %; sweep runs/s batched vs plain at 1e-4 err",
         "value": round(head["mlups"], 1),
@@ -564,7 +623,8 @@ def main():
                      "traffic": traffic,
                      "kernel": "step_single (" + head["variant"] + ")",
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(head["achieved_gbs"] / copy_gbs, 4),
-                     "bytes_per_lup": head["bytes_per_lup"], "kernel_us": round(head["kernel_ms"] * 1e3, 2)},
+                     "bytes_per_lup": head["bytes_per_lup"], "kernel_us": round(head["kernel_ms"] * 1e3, 2),
+                     "tuning": head["tuning"]},
         "cpu_baseline": cpu,
         "sweep": None if sweep is None else {k: (round(v, 4) if isinstance(v, float) else v) for k, v in sweep.items()},
         "surrogate": surr,

@@ -233,9 +233,10 @@ lbcg_status lbcg_variant_select(lbcg_handle* h, int idx);
  * LBCG_ENONFINITE if the last measurement found a non-finite value. Synchronises. */
 lbcg_status lbcg_variant_time(lbcg_handle* h, int idx, int launches, double* us);
 
-/* Time every variant as lbcg_variant_time does, select the fastest, and return its index and
- * time (either output may be NULL). The state advances by (launches + 1) x lbcg_variant_count
- * steps. The choice is recorded in the process's tuning cache (see lbcg_batch_autotune), so later
+/* Time every variant as lbcg_variant_time does, in two rounds over all variants (each keeps the
+ * faster of its two times, so that the cache state the previous candidate left does not decide),
+ * select the fastest, and return its index and time (either output may be NULL). The state
+ * advances by 2 x (launches + 1) x lbcg_variant_count steps. The choice is recorded in the process's tuning cache (see lbcg_batch_autotune), so later
  * solvers of the same grid kind, shape, precision and architecture start with it. Synchronises. */
 lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_us);
 
@@ -316,7 +317,8 @@ int64_t lbcg_batch_step_count(const lbcg_batch* b);  /* -1 for NULL */
  * lbcg_batch_variant_time times real batched steps with tiling idx (HIP events on the batch's stream:
  * one untimed step, then `launches` timed ones, the ping-pong copies alternating), so the state
  * advances by launches + 1 steps; the selected tiling is left as it was. lbcg_batch_autotune times
- * every tiling that way (all_us[count] receives each time, may be NULL), selects the fastest and
+ * every tiling that way in two rounds (all_us[count] receives each tiling's faster time, may be
+ * NULL; the state advances by 2 x (launches + 1) x count steps), selects the fastest and
  * records the choice in the process's tuning cache under the kernel kind, precision, GPU
  * architecture and the batch's mix of instance shapes; lbcg_batch_create then starts every batch
  * with the same key on that tiling. With the environment variable LBCG_TUNE_CACHE naming a file,

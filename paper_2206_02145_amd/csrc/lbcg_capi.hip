@@ -1212,6 +1212,9 @@ void select_variant(lbcg_handle* h, int idx) {
 // ping-pong parity alternating as in lbcg_step (re-reading one input copy would let the
 // last-level cache hold part of it and flatter the variant). The state advances by launches + 1
 // steps of variant idx.
+// Rounds of the autotuners over all candidates; each candidate keeps its fastest time.
+constexpr int TUNE_ROUNDS = 2;
+
 double time_variant(lbcg_handle* h, int idx, int launches) {
     if (h->nonfinite) throw Error(LBCG_ENONFINITE, "the last measurement found a non-finite value");
     const int keep = h->variant;
@@ -1258,15 +1261,14 @@ lbcg_status lbcg_autotune(lbcg_handle* h, int launches, int* best, double* best_
     return guarded([&] {
         if (!h) throw Error(LBCG_EINVAL, "handle is NULL");
         if (launches < 1) throw Error(LBCG_EINVAL, "launches must be >= 1");
+        const int nv = (int)h->variants.size();
+        std::vector<double> t(nv, 1e300);
+        for (int r = 0; r < TUNE_ROUNDS; r++)
+            for (int i = 0; i < nv; i++) t[i] = std::min(t[i], time_variant(h, i, launches));
         int bi = 0;
-        double bt = 1e300;
-        for (int i = 0; i < (int)h->variants.size(); i++) {
-            const double t = time_variant(h, i, launches);
-            if (t < bt) {
-                bt = t;
-                bi = i;
-            }
-        }
+        for (int i = 1; i < nv; i++)
+            if (t[i] < t[bi]) bi = i;
+        const double bt = t[bi];
         select_variant(h, bi);
         tune_store(grid_key(h->p), variant_name(h->variants[bi]));
         if (best) *best = bi;
@@ -1675,16 +1677,16 @@ lbcg_status lbcg_batch_autotune(lbcg_batch* b, int launches, int* best, double* 
     return guarded([&] {
         if (!b) throw Error(LBCG_EINVAL, "batch is NULL");
         if (launches < 1) throw Error(LBCG_EINVAL, "launches must be >= 1");
+        const int nv = (int)b->kits->size();
+        std::vector<double> t(nv, 1e300);
+        for (int r = 0; r < TUNE_ROUNDS; r++)
+            for (int i = 0; i < nv; i++) t[i] = std::min(t[i], batch_time_variant(b, i, launches));
         int bi = 0;
-        double bt = 1e300;
-        for (int i = 0; i < (int)b->kits->size(); i++) {
-            const double t = batch_time_variant(b, i, launches);
-            if (all_us) all_us[i] = t;
-            if (t < bt) {
-                bt = t;
-                bi = i;
-            }
+        for (int i = 0; i < nv; i++) {
+            if (all_us) all_us[i] = t[i];
+            if (t[i] < t[bi]) bi = i;
         }
+        const double bt = t[bi];
         batch_select(b, bi);
         tune_store(batch_key(b->n, b->p.data()), batch_variant_name(b, bi));
         if (best) *best = bi;

@@ -333,7 +333,8 @@ class Solver:
         return us.value
 
     def autotune(self, launches: int = 20):
-        """Select the fastest variant; the state advances by (launches + 1) steps per variant."""
+        """Select the fastest variant (two timing rounds); the state advances by 2 (launches + 1)
+        steps per variant."""
         best = ctypes.c_int()
         us = ctypes.c_double()
         check(lib().lbcg_autotune(self.handle, int(launches), ctypes.byref(best), ctypes.byref(us)), "lbcg_autotune")
