@@ -105,6 +105,32 @@ def test_full_size_pointwise_fp32(lb, case, step):
         s.close()
 
 
+@pytest.mark.parametrize("case,step,prec", [("c2", None, "fp32"), ("c3", 4000, "fp32"), ("c3", 4000, "fp16shift")])
+def test_full_size_in_the_timed_configuration(lb, case, step, prec):
+    """The launch configuration bench.py times: the solver autotuned as the bench does (every tiling,
+    two rounds of 20 real steps, so the run itself passes through all of them), then on the chosen
+    tiling to the stored oracle state, compared pointwise as above."""
+    z, meta, p = load(case, step)
+    steps = meta["steps"]
+    s = lb.Solver(p, prec)
+    best, us = s.autotune(20)
+    done = s.nstep
+    print(f"[fulllength] {case} {prec} autotuned: {s.variants()[best]} ({us:.1f} us/step) after {done} steps",
+          flush=True)
+    assert 0 < done < steps
+    s.step(steps - done)
+    errs = errors(s, z, p)
+    dL, dVs, dM = aggregates(s, z)
+    print(f"[fulllength] {case} {prec} tuned @{steps}: " + ", ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
+          f"; max |dL| {dL:.2e} cells; Vs {dVs:.2e}; M' {dM:.2e}", flush=True)
+    bar = 1e-4 if prec == "fp32" else 5e-2
+    for k, v in errs.items():
+        assert v <= bar, (case, prec, k, v)
+    if prec == "fp32":
+        assert dL <= 0.05 and dVs <= 1e-5
+    s.close()
+
+
 def test_full_length_flow_aggregates_fp32(lb):
     z, meta, p = load("c3")
     steps = meta["steps"]
