@@ -150,3 +150,25 @@ def test_workspace_holds_the_padded_row_pitch():
         es = 8 if prec == "fp64" else 4
         assert a >= (2 * 7 * 2 + 19 * 2 + 1) * 128 * 20 * 10 * es, prec
         assert c < a and abs(a - b) < 128 * 1024, (prec, a, b, c)  # the dense staging area differs
+
+
+def test_batch_sizes_and_mixes_are_validated():
+    """A batch of no instances, more than 65535, instances of different kinds, or instances with
+    walls has no workspace size (0) and is refused by lbcg_batch_create before any device call."""
+    L = lbcg.lib()
+
+    def arr(plist, prec="fp32"):
+        return (lbcg.lbcg_params * len(plist))(*[lbcg.make_params(p, prec) for p in plist])
+
+    one = [W.sweep_instance(96, 0.3, 8.0, 0.02)]
+    assert L.lbcg_batch_workspace_bytes(1, arr(one)) > 0
+    assert L.lbcg_batch_workspace_bytes(0, arr(one)) == 0
+    assert L.lbcg_batch_workspace_bytes(65536, arr(one)) == 0
+    mixed = one + [W.params(dim=2, nx=64, ny=64)]  # the second has no flow
+    assert L.lbcg_batch_workspace_bytes(2, arr(mixed)) == 0
+    walled = [dict(one[0], walls=1)]
+    assert L.lbcg_batch_workspace_bytes(1, arr(walled)) == 0
+    out = ctypes.c_void_p()
+    for n, plist in ((0, one), (2, mixed), (1, walled)):
+        code = L.lbcg_batch_create(n, arr(plist), None, 0, None, ctypes.byref(out))
+        assert lbcg.STATUS[code] == "EINVAL" and not out.value, (n, code)
