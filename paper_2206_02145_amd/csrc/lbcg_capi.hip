@@ -380,15 +380,21 @@ void block_variants(std::vector<Variant>& v, bool large, int gdef) {
         // first = default: 64 x 2 x 4 (one wavefront per x-row); when the two population copies
         // exceed the last-level cache, streaming loads and stores of g and f with h and phi_prev
         // kept in the caches, and gdef planes of g with them (the fastest measured on the
-        // 192 x 128 x 128 flow grid, also with binary16 flow storage); below that size, the
-        // default policy everywhere
-        if (large) {
+        // 192 x 128 x 128 flow grid, also with binary16 flow storage); when not even h and phi_prev
+        // fit (gdef < 0), streaming stores in bands of 16 z tile-layers, whose z-halo re-reads of
+        // h then still find it in L2 (384 x 256 x 256: 1464 against 1583 us for h kept in the
+        // caches; 512 x 512 x 256: 3832 against 3957); below the cache size, the default policy
+        if (large && gdef < 0) {
+            band(a2, 16);
+            for (const Ops* o : {&k0, &k2, &k3, &a2, &a3, &a0, &a1, &d0}) add(*o);
+        } else if (large) {
             add(*kd);
             for (const Ops* o : {&k0, &k2, &k3})
                 if (o != kd) add(*o);
             for (const Ops* o : {&a2, &a3, &a0, &a1, &d0}) add(*o);
         } else for (const Ops* o : {&a0, &a1, &a2, &a3, &d0, &k0, &k2, &k3}) add(*o);
         for (int zb : {2, 4, 8}) band(large ? a2 : a0, zb);
+        if (!(large && gdef < 0)) band(large ? a2 : a0, 16);
         band(large ? a3 : a1, 4);
         for (const Ops* o : {&b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
     }
@@ -410,9 +416,17 @@ std::vector<Variant> wall_variants(bool large, int gdef) {
         static const Ops b = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 0, true>::ops();
         static const Ops k = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, true, false, 0>::ops();
         static const Ops k2 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, true, false, 0, 2>::ops();
+        Tiling banded = b.tiling;  // streaming stores in bands of 16 z tile-layers (see block_variants)
+        banded.zband = 16;
+        if (large && gdef < 0) {
+            v.push_back({&b, banded});
+            for (const Ops* o : {&k, &k2, &b, &a}) add(*o);
+            return v;
+        }
         if (large && gdef >= 2) for (const Ops* o : {&k2, &k, &b, &a}) add(*o);
         else if (large) for (const Ops* o : {&k, &k2, &b, &a}) add(*o);
         else for (const Ops* o : {&a, &b, &k, &k2}) add(*o);
+        v.push_back({&b, banded});
     }
     return v;
 }
@@ -443,15 +457,21 @@ std::vector<Variant> chm_variants(bool large, bool walls, int gdef) {
         static const Ops k = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, false, true, 0>::ops();
         static const Ops k2 = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, false, true, 0, 2>::ops();
         static const Ops wk = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, true, true, 0>::ops();
+        Tiling banded = a2.tiling;  // streaming stores in bands of 16 z tile-layers (see block_variants)
+        banded.zband = 16;
         if (walls && large) {
             add(wk);
             add(w);
         } else if (walls) {
             add(w);
             add(wk);
+        } else if (large && gdef < 0) {
+            v.push_back({&a2, banded});
+            for (const Ops* o : {&k, &k2, &a2, &a3, &a0}) add(*o);
         } else if (large && gdef >= 2) for (const Ops* o : {&k2, &k, &a2, &a3, &a0}) add(*o);
         else if (large) for (const Ops* o : {&k, &k2, &a2, &a3, &a0}) add(*o);
         else for (const Ops* o : {&a0, &a2, &a3, &k, &k2}) add(*o);
+        if (!walls && !(large && gdef < 0)) v.push_back({&a2, banded});
     }
     return v;
 }
@@ -509,13 +529,14 @@ std::vector<Variant> variants_for(int dim, int flow, int prec, int nx, double po
 // while it fits well inside the 256 MB last-level cache: on the 192 x 128 x 128 flow grid 10 planes
 // (126 MB) gained 3.8 %, 11 (138 MB) 5.3 %, 12 (151 MB) lost 2 %, and on 256 x 128 x 128 a ninth
 // plane (151 MB) lost 4 %. The default keeps 3 or 2 planes of g when everything kept stays within
-// 128 MiB, else none; the autotuner can choose otherwise.
+// 128 MiB, else none, and -1 says that not even h and phi_prev fit; the autotuner can choose
+// otherwise.
 constexpr double CACHE_KEEP_BYTES = 128.0 * 1024 * 1024;
 int default_gcache(const lbcg_params& p) {
     const double plane = (double)stored_nodes(&p) * real_size(p.precision);
     for (int k : {3, 2})
         if ((qs_of(p.dim) + 1 + k) * plane <= CACHE_KEEP_BYTES) return k;
-    return 0;
+    return (qs_of(p.dim) + 1) * plane <= CACHE_KEEP_BYTES ? 0 : -1;
 }
 
 double population_bytes(const lbcg_params& p) {
