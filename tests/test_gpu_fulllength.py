@@ -167,10 +167,10 @@ def test_full_length_flow_fp64(lb):
 # sampled node outside the crystal (oracle phi < 0.9: the liquid and the interface, where U enters
 # the phase field through lambda U (1 - phi^2)^2 and sets the growth). Inside the crystal
 # q = 1 - phi = 0 makes tau_U exactly 1/2: the solute lattice there has no diffusion and its
-# non-equilibrium modes are not damped, so every rounding that reaches it stays in the field, above
-# all the last-place noise of psi = phi + 1 ~ 2 that enters through the source -dphi/dt (binary32
-# against binary64 on the GPU after 20000 steps: U off by 6e-5 at crystal nodes where phi is off by
-# 1e-7, 1e-6 in the liquid and at the interface). U over all samples, crystal included, against the oracle:
+# non-equilibrium modes are not damped, so the rounding of the stored solute populations stays in
+# the field (binary32 against binary64 on the GPU after 20000 steps: U off by 6e-5 at crystal nodes
+# where phi is off by 1e-7, 1e-6 in the liquid and at the interface; resolving phi in the crystal
+# as binary64 does leaves U there no better). U over all samples, crystal included, against the oracle:
 # 1.7e-5, 4.9e-5, 1.2e-4, 2.0e-4 and 2.5e-4 at 4000 .. 20000 steps (2.3e-4 at 8000 and 9.3e-4 at
 # 20000 without the compensated closure of the phase-field collision).
 C3R_U_BAR = {4000: 1e-4, 8000: 1e-4, 12000: 1.6e-4, 16000: 2.6e-4, 20000: 3.2e-4}
