@@ -40,9 +40,10 @@ std::vector<BatchKit> kits_of() {
     constexpr int S = sizeof(real) == 8 ? 0 : 2;  // streaming stores in binary32
     std::vector<BatchKit> v;
     if constexpr (DIM == 2) {
-        // binary32 flow: streaming loads and stores of g, f and phi_prev with h kept in the caches
-        // first (the 256 sweep instances' 1 GB exceed the last-level cache; 64 x 8 tiles measured
-        // fastest among these for them: 204.5 against 219 us per step for 64 x 4 streaming stores)
+        // binary32 flow: streaming loads and stores of g and f with h and phi_prev kept in the
+        // caches first (the 256 sweep instances' 1 GB exceed the last-level cache; 64 x 8 and
+        // 64 x 4 tiles measured fastest among these for them, ~199 against 216 us per step for
+        // streaming stores alone)
         if constexpr (FLOW && !CHM && S != 0) v.push_back(BatchImpl<2, FLOW, real, fst, 64, 8, 1, false, 2, CHM, 2, 0>::kit());
         v.push_back(BatchImpl<2, FLOW, real, fst, 64, 4, 1, false, S, CHM>::kit());
         if constexpr (FLOW && !CHM) {

@@ -341,7 +341,7 @@ void block_variants(std::vector<Variant>& v, bool large, int gdef) {
         static const Ops c = BlockOps<2, FLOW, real, fst, 64, 2, 1, true, 2>::ops();
         static const Ops d = BlockOps<2, FLOW, real, fst, 64, 8, 1, false, 2>::ops();
         static const Ops e = BlockOps<2, FLOW, real, fst, 128, 2, 1, false, 2>::ops();
-        // streaming loads and stores of g, f and phi_prev, h kept in the caches (see step_tile)
+        // streaming loads and stores of g and f, h and phi_prev kept in the caches (see step_tile)
         static const Ops k = BlockOps<2, FLOW, real, fst, 64, 4, 1, false, 2, 2, false, false, 0>::ops();
         static const Ops k8 = BlockOps<2, FLOW, real, fst, 64, 8, 1, false, 2, 2, false, false, 0>::ops();
         if (large) for (const Ops* o : {&k, &a, &a0, &b, &c, &d, &e, &k8}) add(*o);
@@ -366,7 +366,7 @@ void block_variants(std::vector<Variant>& v, bool large, int gdef) {
         static const Ops c1 = BlockOps<3, FLOW, real, fst, 32, 8, 2, true>::ops();
         static const Ops c2 = BlockOps<3, FLOW, real, fst, 32, 4, 4, true>::ops();
         static const Ops d0 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2>::ops();
-        // streaming loads and stores of g, f and phi_prev, h kept in the caches (see step_tile)
+        // streaming loads and stores of g and f, h and phi_prev kept in the caches (see step_tile)
         static const Ops k0 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, false, false, 0>::ops();
         // the same with 2 or 3 planes of g kept in the caches as well
         static const Ops k2 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, false, false, 0, 2>::ops();
