@@ -332,7 +332,7 @@ constexpr int MARCH_MAX_NX = 256;
 constexpr double LLC_BYTES = 256.0 * 1024 * 1024;
 
 template <int DIM, bool FLOW, typename real, typename fst>
-void block_variants(std::vector<Variant>& v, bool large, int gdef) {
+void block_variants(std::vector<Variant>& v, bool large, int gdef, int zdef) {
     auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
     if constexpr (DIM == 2) {
         static const Ops a = BlockOps<2, FLOW, real, fst, 64, 4, 1, false, sizeof(real) == 8 ? 0 : 2>::ops();
@@ -381,11 +381,12 @@ void block_variants(std::vector<Variant>& v, bool large, int gdef) {
         // exceed the last-level cache, streaming loads and stores of g and f with h and phi_prev
         // kept in the caches, and gdef planes of g with them (the fastest measured on the
         // 192 x 128 x 128 flow grid, also with binary16 flow storage); when not even h and phi_prev
-        // fit (gdef < 0), streaming stores in bands of 16 z tile-layers, whose z-halo re-reads of
-        // h then still find it in L2 (384 x 256 x 256: 1464 against 1583 us for h kept in the
-        // caches; 512 x 512 x 256: 3832 against 3957); below the cache size, the default policy
+        // fit (gdef < 0), streaming stores in bands of zdef z tile-layers, whose halo re-reads of h
+        // then still find it in L2 (384 x 256 x 256, bands of 16: 1464 against 1583 us for h kept
+        // in the caches; 512 x 512 x 256, bands of 8: 3794 against 3957); below the cache size,
+        // the default policy
         if (large && gdef < 0) {
-            band(a2, 16);
+            band(a2, zdef);
             for (const Ops* o : {&k0, &k2, &k3, &a2, &a3, &a0, &a1, &d0}) add(*o);
         } else if (large) {
             add(*kd);
@@ -393,8 +394,8 @@ void block_variants(std::vector<Variant>& v, bool large, int gdef) {
                 if (o != kd) add(*o);
             for (const Ops* o : {&a2, &a3, &a0, &a1, &d0}) add(*o);
         } else for (const Ops* o : {&a0, &a1, &a2, &a3, &d0, &k0, &k2, &k3}) add(*o);
-        for (int zb : {2, 4, 8}) band(large ? a2 : a0, zb);
-        if (!(large && gdef < 0)) band(large ? a2 : a0, 16);
+        for (int zb : {2, 4, 8, 16})
+            if (!(large && gdef < 0 && zb == zdef)) band(large ? a2 : a0, zb);
         band(large ? a3 : a1, 4);
         for (const Ops* o : {&b0, &b1, &b2, &b3, &c0, &c1, &c2}) add(*o);
     }
@@ -402,7 +403,7 @@ void block_variants(std::vector<Variant>& v, bool large, int gdef) {
 
 // Tilings of the kernel that honours a wall mask (the first is the default).
 template <int DIM, bool FLOW, typename real, typename fst>
-std::vector<Variant> wall_variants(bool large, int gdef) {
+std::vector<Variant> wall_variants(bool large, int gdef, int zdef) {
     std::vector<Variant> v;
     auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
     if constexpr (DIM == 2) {
@@ -416,8 +417,8 @@ std::vector<Variant> wall_variants(bool large, int gdef) {
         static const Ops b = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 0, true>::ops();
         static const Ops k = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, true, false, 0>::ops();
         static const Ops k2 = BlockOps<3, FLOW, real, fst, 64, 2, 4, false, 2, 2, true, false, 0, 2>::ops();
-        Tiling banded = b.tiling;  // streaming stores in bands of 16 z tile-layers (see block_variants)
-        banded.zband = 16;
+        Tiling banded = b.tiling;  // streaming stores in bands of z tile-layers (see block_variants)
+        banded.zband = zdef;
         if (large && gdef < 0) {
             v.push_back({&b, banded});
             for (const Ops* o : {&k, &k2, &b, &a}) add(*o);
@@ -433,7 +434,7 @@ std::vector<Variant> wall_variants(bool large, int gdef) {
 
 // Tilings of the central-Hermite MRT flow kernel, with or without walls (the first is the default).
 template <int DIM, typename real, typename fst>
-std::vector<Variant> chm_variants(bool large, bool walls, int gdef) {
+std::vector<Variant> chm_variants(bool large, bool walls, int gdef, int zdef) {
     std::vector<Variant> v;
     auto add = [&](const Ops& o) { v.push_back({&o, o.tiling}); };
     if constexpr (DIM == 2) {
@@ -457,8 +458,8 @@ std::vector<Variant> chm_variants(bool large, bool walls, int gdef) {
         static const Ops k = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, false, true, 0>::ops();
         static const Ops k2 = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, false, true, 0, 2>::ops();
         static const Ops wk = BlockOps<3, true, real, fst, 64, 2, 4, false, 2, 2, true, true, 0>::ops();
-        Tiling banded = a2.tiling;  // streaming stores in bands of 16 z tile-layers (see block_variants)
-        banded.zband = 16;
+        Tiling banded = a2.tiling;  // streaming stores in bands of z tile-layers (see block_variants)
+        banded.zband = zdef;
         if (walls && large) {
             add(wk);
             add(w);
@@ -477,13 +478,13 @@ std::vector<Variant> chm_variants(bool large, bool walls, int gdef) {
 }
 
 template <int DIM, bool FLOW, typename real, typename fst>
-std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls, bool chm, int gdef) {
+std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls, bool chm, int gdef, int zdef) {
     if constexpr (FLOW) {
-        if (chm) return chm_variants<DIM, real, fst>(pop_bytes > LLC_BYTES, walls, gdef);
+        if (chm) return chm_variants<DIM, real, fst>(pop_bytes > LLC_BYTES, walls, gdef, zdef);
     }
-    if (walls) return wall_variants<DIM, FLOW, real, fst>(pop_bytes > LLC_BYTES, gdef);
+    if (walls) return wall_variants<DIM, FLOW, real, fst>(pop_bytes > LLC_BYTES, gdef, zdef);
     std::vector<Variant> v;
-    block_variants<DIM, FLOW, real, fst>(v, pop_bytes > LLC_BYTES, gdef);
+    block_variants<DIM, FLOW, real, fst>(v, pop_bytes > LLC_BYTES, gdef, zdef);
     if constexpr (DIM == 3) {
         if (nx > 0 && nx <= MARCH_MAX_NX) {  // (nx = 0: not offered)
             // z-marching kernels (rows of up to 256 nodes) as further candidates
@@ -508,21 +509,22 @@ std::vector<Variant> variants_of(int nx, double pop_bytes, bool walls, bool chm,
 }
 
 // Candidate tilings for one grid kind; the first is the default. pop_bytes: both population copies;
-// gdef: planes of g the default keeps in the caches beside h and phi_prev (default_gcache).
+// gdef: planes of g the default keeps in the caches beside h and phi_prev (default_gcache); zdef:
+// the z-band of the default where not even h and phi_prev fit (default_zband).
 std::vector<Variant> variants_for(int dim, int flow, int prec, int nx, double pop_bytes, bool walls, bool chm,
-                                  int gdef) {
+                                  int gdef, int zdef) {
     const double b = pop_bytes;
-    const int g = gdef;
+    const int g = gdef, zb = zdef;
     if (dim == 2) {
-        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx, b, walls, false, g) : variants_of<2, false, float, float>(nx, b, walls, false, g);
-        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx, b, walls, chm, g)
-               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx, b, walls, chm, g)
-                                   : variants_of<2, true, float, __half>(nx, b, walls, chm, g);
+        if (!flow) return prec == LBCG_FP64 ? variants_of<2, false, double, double>(nx, b, walls, false, g, zb) : variants_of<2, false, float, float>(nx, b, walls, false, g, zb);
+        return prec == LBCG_FP64   ? variants_of<2, true, double, double>(nx, b, walls, chm, g, zb)
+               : prec == LBCG_FP32 ? variants_of<2, true, float, float>(nx, b, walls, chm, g, zb)
+                                   : variants_of<2, true, float, __half>(nx, b, walls, chm, g, zb);
     }
-    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx, b, walls, false, g) : variants_of<3, false, float, float>(nx, b, walls, false, g);
-    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx, b, walls, chm, g)
-           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx, b, walls, chm, g)
-                               : variants_of<3, true, float, __half>(nx, b, walls, chm, g);
+    if (!flow) return prec == LBCG_FP64 ? variants_of<3, false, double, double>(nx, b, walls, false, g, zb) : variants_of<3, false, float, float>(nx, b, walls, false, g, zb);
+    return prec == LBCG_FP64   ? variants_of<3, true, double, double>(nx, b, walls, chm, g, zb)
+           : prec == LBCG_FP32 ? variants_of<3, true, float, float>(nx, b, walls, chm, g, zb)
+                               : variants_of<3, true, float, __half>(nx, b, walls, chm, g, zb);
 }
 
 // What the step keeps in the caches between steps (h, phi_prev and the first planes of g) pays only
@@ -537,6 +539,18 @@ int default_gcache(const lbcg_params& p) {
     for (int k : {3, 2})
         if ((qs_of(p.dim) + 1 + k) * plane <= CACHE_KEEP_BYTES) return k;
     return (qs_of(p.dim) + 1) * plane <= CACHE_KEEP_BYTES ? 0 : -1;
+}
+
+// The z-band of the tile order where h no longer stays in the caches between steps: a tile's y
+// neighbours then run (x tiles) x (band) tiles apart, and both they and its z neighbours should
+// still be among the tiles that an XCD holds at once (some 96 of 64 x 2 x 4, whose halo rows then
+// come from its L2): the largest power of two up to 96 / (x tiles), between 4 and 16 (measured:
+// 6 x tiles, 16 best; 8 x tiles, 8 best).
+int default_zband(const lbcg_params& p) {
+    const int ntx = (p.nx + 63) / 64;
+    int b = 16;
+    while (b > 4 && b * ntx > 96) b /= 2;
+    return b;
 }
 
 double population_bytes(const lbcg_params& p) {
@@ -838,7 +852,8 @@ lbcg_status lbcg_create(const lbcg_params* p, void* dev_workspace, size_t bytes,
         const bool chm = p->collision == LBCG_COLLISION_CHMRT;
         hdl->variants = variants_for(p->dim, p->flow, p->precision,
                                      (p->xbc == LBCG_INFLOW_PRESSURE || chm) ? 0 : p->nx,  // (0: no z-marching tiling)
-                                     population_bytes(*p), p->walls != 0, chm, default_gcache(*p));
+                                     population_bytes(*p), p->walls != 0, chm, default_gcache(*p),
+                                     default_zband(*p));
         hdl->variant = 0;
         std::string tuned;  // a tiling the autotuner chose for this grid earlier in the process
         if (tune_lookup(grid_key(*p), tuned)) hdl->variant = std::max(0, variant_index_by_name(hdl->variants, tuned));
@@ -1473,7 +1488,7 @@ lbcg_status lbcg_batch_create(int n, const lbcg_params* p, void* dev_workspace, 
             for (int k = 0; k < (int)b->kits->size(); k++)
                 if (variant_name(Variant{nullptr, (*b->kits)[k].tiling}) == tuned) b->kit_idx = k;
         b->kit = &(*b->kits)[b->kit_idx];
-        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0, false, false, 0)[0].ops;
+        b->common = variants_for(p[0].dim, p[0].flow, p[0].precision, p[0].nx, 0.0, false, false, 0, 16)[0].ops;
         b->par = 0;
         b->nstep = 0;
         int tiles = 0;
