@@ -131,13 +131,17 @@ def test_full_size_in_the_timed_configuration(lb, case, step, prec):
     s.close()
 
 
-def test_full_length_flow_aggregates_fp32(lb):
+@pytest.mark.parametrize("prec", ["fp32", "fp16shift"])
+def test_full_length_flow_aggregates(lb, prec):
+    """After the configuration's 20000 steps, what the amplification leaves alone: the crystal
+    extents, the solid volume and M' (measured: binary32 0.11 cells, 1.3e-4, 1.5e-4; binary16 flow
+    storage 0.12 cells, 4.4e-5, 1.3e-5)."""
     z, meta, p = load("c3")
     steps = meta["steps"]
-    s = run(lb, p, "fp32", steps)
+    s = run(lb, p, prec, steps)
     errs = errors(s, z, p)
     dL, dVs, dM = aggregates(s, z)
-    print(f"[fulllength] c3 fp32 @{steps} pointwise (amplified, not asserted): " +
+    print(f"[fulllength] c3 {prec} @{steps} pointwise (amplified, not asserted): " +
           ", ".join(f"{k}={v:.2e}" for k, v in errs.items()) +
           f"; aggregates: max |dL| {dL:.3f} cells, Vs {dVs:.2e}, M' {dM:.2e}", flush=True)
     assert dL <= 1.0 and dVs <= 2e-3 and dM <= 1e-3
