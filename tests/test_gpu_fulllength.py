@@ -180,8 +180,12 @@ def test_full_length_flow_fp64(lb):
 C3R_U_BAR = {4000: 1e-4, 8000: 1e-4, 12000: 1.6e-4, 16000: 2.6e-4, 20000: 3.2e-4}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "fp16shift"])
 def test_reduced_flow_grid_every_4000_steps(lb, prec):
+    """The 96x64x64 flow grid at eps = 0.02 against the oracle's state every 4000 steps through
+    20000: binary64 to 1e-10; binary32 as the comment above says; binary16 flow storage within the
+    mode's 5e-2 per field (measured at 20000 steps: rho 1.9e-2, phi 1.6e-2, u 1.6e-2, U 3.3e-3) and
+    0.1 cells in the extents (3.6e-2)."""
     snaps = {}
     for step in (4000, 8000, 12000, 16000, None):
         z, meta, p = load("c3r", step)
@@ -207,6 +211,10 @@ def test_reduced_flow_grid_every_4000_steps(lb, prec):
             for k, v in errs.items():
                 assert v <= 1e-10, (step, k, v)
             assert dL <= 1e-8 and dVs <= 1e-11 and dM <= 1e-11
+        elif prec == "fp16shift":
+            for k, v in errs.items():
+                assert v <= 5e-2, (step, k, v)
+            assert dL <= 0.1
         else:
             for k, v in errs.items():
                 assert v <= (C3R_U_BAR[step] if k == "U" else 1e-4), (step, k, v)
